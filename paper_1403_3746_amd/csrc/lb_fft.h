@@ -1,0 +1,257 @@
+// Line FFT engine for gfx950: Stockham autosort mixed-radix (2, 3, 4, 8) transforms of complex
+// lines of length N held R elements per thread, exchanged through LDS between passes.
+//
+// A line is processed by N/R consecutive "line threads"; thread t holds elements t + m*(N/R),
+// m = 0..R-1 ("natural" order) on entry and the transform coefficients X[t + m*(N/R)] on exit.
+// Passes whose radix equals R read (first pass) or write (last pass) registers directly; all
+// other passes go through the line's LDS region of N complex words.  Twiddles come from a
+// float64-generated table exp(-2 pi i k/N), k = 0..N-1, rounded to the working precision.
+#pragma once
+#include <hip/hip_runtime.h>
+
+namespace lbfft {
+
+template <typename T>
+struct cpx {
+    T re, im;
+};
+
+template <typename T>
+__device__ __forceinline__ cpx<T> cadd(cpx<T> a, cpx<T> b) { return {a.re + b.re, a.im + b.im}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> csub(cpx<T> a, cpx<T> b) { return {a.re - b.re, a.im - b.im}; }
+template <typename T>
+__device__ __forceinline__ cpx<T> cmul(cpx<T> a, cpx<T> b) {
+    return {a.re * b.re - a.im * b.im, a.re * b.im + a.im * b.re};
+}
+// a * conj(b)
+template <typename T>
+__device__ __forceinline__ cpx<T> cmulc(cpx<T> a, cpx<T> b) {
+    return {a.re * b.re + a.im * b.im, a.im * b.re - a.re * b.im};
+}
+// multiply by -i (forward) or +i (inverse)
+template <typename T, bool INV>
+__device__ __forceinline__ cpx<T> rot90(cpx<T> a) {
+    if (INV) return {-a.im, a.re};
+    return {a.im, -a.re};
+}
+
+// In-register DFT of size r, outputs in natural order.  Forward kernel exp(-2 pi i pq/r),
+// inverse exp(+2 pi i pq/r).
+template <typename T, int r, bool INV>
+struct Dft;
+
+template <typename T, bool INV>
+struct Dft<T, 2, INV> {
+    __device__ __forceinline__ static void run(cpx<T>* v) {
+        cpx<T> a = v[0], b = v[1];
+        v[0] = cadd(a, b);
+        v[1] = csub(a, b);
+    }
+};
+
+template <typename T, bool INV>
+struct Dft<T, 3, INV> {
+    __device__ __forceinline__ static void run(cpx<T>* v) {
+        const T h = T(0.86602540378443864676);  // sqrt(3)/2
+        cpx<T> s = cadd(v[1], v[2]);
+        cpx<T> d = csub(v[1], v[2]);
+        cpx<T> x0 = v[0];
+        cpx<T> t = {x0.re - T(0.5) * s.re, x0.im - T(0.5) * s.im};
+        cpx<T> rd = rot90<T, INV>(d);   // -i d (forward), +i d (inverse)
+        v[0] = cadd(x0, s);
+        v[1] = {t.re + h * rd.re, t.im + h * rd.im};
+        v[2] = {t.re - h * rd.re, t.im - h * rd.im};
+    }
+};
+
+template <typename T, bool INV>
+struct Dft<T, 4, INV> {
+    __device__ __forceinline__ static void run(cpx<T>* v) {
+        cpx<T> a0 = cadd(v[0], v[2]), a1 = csub(v[0], v[2]);
+        cpx<T> a2 = cadd(v[1], v[3]), a3 = rot90<T, INV>(csub(v[1], v[3]));
+        v[0] = cadd(a0, a2);
+        v[2] = csub(a0, a2);
+        v[1] = cadd(a1, a3);
+        v[3] = csub(a1, a3);
+    }
+};
+
+template <typename T, bool INV>
+struct Dft<T, 8, INV> {
+    __device__ __forceinline__ static void run(cpx<T>* v) {
+        const T s = T(0.70710678118654752440);
+        // split into even/odd halves of the decimation-in-frequency step
+        cpx<T> a[4], b[4];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            a[k] = cadd(v[k], v[k + 4]);
+            b[k] = csub(v[k], v[k + 4]);
+        }
+        // b[k] *= w8^k, w8 = exp(-+ i pi/4)
+        {
+            cpx<T> x = b[1];
+            // forward: (1 - i)/sqrt2 ; inverse: (1 + i)/sqrt2
+            b[1] = INV ? cpx<T>{s * (x.re - x.im), s * (x.re + x.im)}
+                       : cpx<T>{s * (x.re + x.im), s * (x.im - x.re)};
+            b[2] = rot90<T, INV>(b[2]);
+            x = b[3];
+            // forward: (-1 - i)/sqrt2 ; inverse: (-1 + i)/sqrt2
+            b[3] = INV ? cpx<T>{s * (-x.re - x.im), s * (x.re - x.im)}
+                       : cpx<T>{s * (x.im - x.re), s * (-x.re - x.im)};
+        }
+        Dft<T, 4, INV>::run(a);
+        Dft<T, 4, INV>::run(b);
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+            v[2 * k] = a[k];
+            v[2 * k + 1] = b[k];
+        }
+    }
+};
+
+// ---------------------------------------------------------------------------------------
+// Radix plans.  R (elements per thread) and the pass radices are compile-time functions of N.
+// Supported N: 1, 2 and 2^a, 3*2^a for 8 <= N <= 2048.
+constexpr int ilog2c(int n) { return n <= 1 ? 0 : 1 + ilog2c(n / 2); }
+
+constexpr int default_R(int N) {
+    return N <= 2 ? N : (N % 3 == 0 ? 12 : (N == 16 || N == 32 ? 4 : 8));
+}
+
+struct Plan {
+    int np;
+    int r[12];
+};
+
+constexpr Plan make_plan(int N, int R) {
+    Plan p{0, {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0}};
+    if (N <= 1) return p;
+    if (N == 2) {
+        p.np = 1;
+        p.r[0] = 2;
+        return p;
+    }
+    int three = (N % 3 == 0) ? 1 : 0;
+    int pow2 = three ? N / 3 : N;
+    int big = (R == 12) ? 4 : R;
+    int nbig = 0;
+    while (pow2 >= big && pow2 % big == 0) {
+        pow2 /= big;
+        ++nbig;
+    }
+    int rem = pow2;  // 1, 2 or 4
+    // first a big radix, then the odd factors, then the remaining big radices
+    if (nbig > 0) {
+        p.r[p.np++] = big;
+        --nbig;
+    }
+    if (three) p.r[p.np++] = 3;
+    if (rem > 1) p.r[p.np++] = rem;
+    while (nbig-- > 0) p.r[p.np++] = big;
+    return p;
+}
+
+constexpr int plan_ns(const Plan& p, int s) {
+    int ns = 1;
+    for (int i = 0; i < s; ++i) ns *= p.r[i];
+    return ns;
+}
+
+template <typename T>
+__device__ __forceinline__ cpx<T> ld_tw(const cpx<T>* __restrict__ tw, int idx) {
+    return tw[idx];
+}
+
+// One Stockham pass of radix r with Ns = product of the previous radices.
+template <typename T, int N, int R, int r, int Ns, bool INV, bool FROM_REG, bool TO_REG>
+__device__ __forceinline__ void stockham_pass(cpx<T> (&v)[R], cpx<T>* lds, int t,
+                                              const cpx<T>* __restrict__ tw) {
+    constexpr int TPL = N / R;
+    constexpr int NB = R / r;
+    static_assert(R % r == 0, "radix must divide R");
+    cpx<T> a[R];
+    if constexpr (FROM_REG) {
+        static_assert(NB == 1, "register-direct pass needs r == R");
+#pragma unroll
+        for (int q = 0; q < r; ++q) a[q] = v[q];
+    } else {
+#pragma unroll
+        for (int b = 0; b < NB; ++b) {
+            const int j = t + b * TPL;
+#pragma unroll
+            for (int q = 0; q < r; ++q) a[b * r + q] = lds[j + q * (N / r)];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int j = t + b * TPL;
+        const int k = j % Ns;
+        if constexpr (Ns > 1) {
+#pragma unroll
+            for (int q = 1; q < r; ++q) {
+                const cpx<T> w = ld_tw(tw, k * q * (N / (Ns * r)));
+                a[b * r + q] = INV ? cmulc(a[b * r + q], w) : cmul(a[b * r + q], w);
+            }
+        }
+        Dft<T, r, INV>::run(&a[b * r]);
+        if constexpr (TO_REG) {
+            static_assert(NB == 1, "register-direct pass needs r == R");
+#pragma unroll
+            for (int q = 0; q < r; ++q) v[q] = a[q];
+        } else {
+            const int base = (j / Ns) * Ns * r + k;
+#pragma unroll
+            for (int q = 0; q < r; ++q) lds[base + q * Ns] = a[b * r + q];
+        }
+    }
+    if constexpr (!TO_REG) __syncthreads();
+}
+
+template <typename T, int N, int R, bool INV>
+struct LineFFT {
+    static constexpr Plan P = make_plan(N, R);
+    static constexpr int TPL = N / R;
+
+    template <int s>
+    __device__ __forceinline__ static void passes(cpx<T> (&v)[R], cpx<T>* lds, int t,
+                                                  const cpx<T>* __restrict__ tw) {
+        if constexpr (s < P.np) {
+            constexpr int r = P.r[s];
+            constexpr int Ns = plan_ns(P, s);
+            constexpr bool first = (s == 0);
+            constexpr bool last = (s == P.np - 1);
+            constexpr bool from_reg = first && (r == R);
+            constexpr bool to_reg = last && (r == R);
+            stockham_pass<T, N, R, r, Ns, INV, from_reg, to_reg>(v, lds, t, tw);
+            passes<s + 1>(v, lds, t, tw);
+        }
+    }
+
+    // Transform the line in place: v[m] = x[t + m*TPL] on entry, X[t + m*TPL] on exit.
+    // All threads of the workgroup must call this together (it contains barriers).
+    __device__ __forceinline__ static void run(cpx<T> (&v)[R], cpx<T>* lds, int t,
+                                               const cpx<T>* __restrict__ tw) {
+        if constexpr (P.np == 0) {
+            return;
+        } else {
+            constexpr bool first_reg = (P.r[0] == R);
+            constexpr bool last_reg = (P.r[P.np - 1] == R);
+            if constexpr (!first_reg) {
+#pragma unroll
+                for (int m = 0; m < R; ++m) lds[t + m * TPL] = v[m];
+                __syncthreads();
+            }
+            passes<0>(v, lds, t, tw);
+            if constexpr (!last_reg) {
+#pragma unroll
+                for (int m = 0; m < R; ++m) v[m] = lds[t + m * TPL];
+            }
+            // the next transform may write LDS that slower threads are still reading
+            if constexpr (!(P.np == 1 && first_reg && last_reg)) __syncthreads();
+        }
+    }
+};
+
+}  // namespace lbfft

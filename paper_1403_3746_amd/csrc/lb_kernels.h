@@ -1,0 +1,485 @@
+// Kernel templates of the lbfft library (gfx950).  Instantiated per precision and line length
+// in lb_lines_*.hip and lb_pointwise.hip.
+//
+// One Runge-Kutta stage R(f) (Eq. 1, Sec. 2.3) runs as:
+//   moments      pointwise   f -> rho, u, T                              (Sec. 2.1)
+//   macro X1     x lines     d_x, d_xx of rho, T, u                      (Eq. 3)
+//   macro Y1     y lines     d_y terms, lap rho, grad(div u)             (Eq. 3)
+//   stress       pointwise   S, C without C_q, q rho T grad T            (Eq. 2, Sec. 2.2)
+//   macro X2/Y2  x, y lines  B = div S/(rho T), C + C_q                  (Eq. 2)
+//   pop X        x lines     per population: v_x d_x f, f^eq, I_i, BGK, RK axpy -> final (axis-x
+//                            populations) or partial (the rest)
+//   pop Y        y lines     per population: add -c v_y d_y f to the partial -> final
+// Line passes pack two real lines (rows 2l, 2l+1 or columns 2l, 2l+1) into one complex line,
+// which is exact because every spectral multiplier used is Hermitian (m(-k) = conj m(k)).
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "lb_fft.h"
+#include "lb_types.h"
+
+namespace lbfft {
+
+// ---------------------------------------------------------------------------------------
+// Launch geometry of the line passes.
+template <typename T, int N, int DIR>
+struct LineCfg {
+    static constexpr int R = default_R(N);
+    static constexpr int TPL = N / R;
+    static constexpr int CB = 2 * (int)sizeof(T);  // bytes of one complex word
+    static constexpr int lpw_x() {
+        int l = 256 / TPL;
+        return l < 1 ? 1 : l;
+    }
+    static constexpr int pow2_floor(int x) {
+        int p = 1;
+        while (p * 2 <= x) p *= 2;
+        return p;
+    }
+    static constexpr int lpw_y() {
+        int want = 128 / CB;                    // 128-byte row segments
+        int small = 256 / TPL;                  // keep >= 256 threads for short lines
+        if (small > want) want = small;
+        int by_thr = 1024 / TPL;
+        int by_lds = (128 * 1024) / (N * CB);
+        int l = want;
+        if (l > by_thr) l = by_thr;
+        if (l > by_lds) l = by_lds;
+        l = pow2_floor(l < 1 ? 1 : l);
+        return l;
+    }
+    static constexpr int LPW = DIR == 0 ? lpw_x() : lpw_y();
+    static constexpr int WG = LPW * TPL;
+    static constexpr int LDS = LPW * N;   // complex words
+};
+
+// Decode the flat block index into (instance, tile, job).  Blocks of the same (instance, tile)
+// group land on the same XCD (workgroups are dealt to the 8 XCDs round-robin) so that their
+// shared coefficient reads hit one L2.
+struct BlockWork {
+    int inst_local, tile, job;
+    bool valid;
+};
+
+__device__ __forceinline__ BlockWork decode_block(int ngroups, int ntiles, int njobs) {
+    const int b = blockIdx.x;
+    const int xcd = b & 7;
+    const int slot = b >> 3;
+    const int group = (slot / njobs) * 8 + xcd;
+    BlockWork w;
+    w.job = slot % njobs;
+    w.valid = group < ngroups;
+    w.inst_local = group / ntiles;
+    w.tile = group % ntiles;
+    return w;
+}
+
+template <typename T>
+struct vec2 {
+    T a, b;
+};
+
+// Addressing of the two real lines packed into complex line `line` at position p.
+template <int DIR>
+struct LineAddr {
+    // element index of the real part (re) and imaginary part (im) of position p
+    __device__ __forceinline__ static int64_t re(int line, int p, int nx) {
+        return DIR == 0 ? (int64_t)(2 * line) * nx + p : (int64_t)p * nx + 2 * line;
+    }
+    __device__ __forceinline__ static int64_t im(int line, int p, int nx) {
+        return DIR == 0 ? (int64_t)(2 * line + 1) * nx + p : (int64_t)p * nx + 2 * line + 1;
+    }
+};
+
+template <typename T, int DIR, int R, int TPL>
+__device__ __forceinline__ void load_line(const T* __restrict__ g, cpx<T> (&v)[R], int line,
+                                          int t, int nx, int ny, bool active) {
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        const int p = t + m * TPL;
+        cpx<T> z = {T(0), T(0)};
+        if (active) {
+            if constexpr (DIR == 0) {
+                z.re = g[LineAddr<0>::re(line, p, nx)];
+                if (2 * line + 1 < ny) z.im = g[LineAddr<0>::im(line, p, nx)];
+            } else {
+                const vec2<T> w = *reinterpret_cast<const vec2<T>*>(g + LineAddr<1>::re(line, p, nx));
+                z.re = w.a;
+                z.im = w.b;
+            }
+        }
+        v[m] = z;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Macroscopic line pass driven by a job table.
+template <typename T, int N, int DIR>
+__global__ void __launch_bounds__((LineCfg<T, N, DIR>::WG))
+macro_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, int ngroups,
+           int ntiles, const JobDesc* __restrict__ jobs, int njobs) {
+    using C = LineCfg<T, N, DIR>;
+    constexpr int R = C::R, TPL = C::TPL, LPW = C::LPW;
+    __shared__ cpx<T> lds_all[C::LDS];
+    const BlockWork w = decode_block(ngroups, ntiles, njobs);
+    if (!w.valid) return;
+    const InstDesc& I = insts[ilist[w.inst_local]];
+    const JobDesc J = jobs[w.job];
+    if (J.flag_q && I.q == 0.0) return;
+
+    const int tid = threadIdx.x;
+    const int l = DIR == 0 ? tid / TPL : tid % LPW;
+    const int t = DIR == 0 ? tid % TPL : tid / LPW;
+    const int line = w.tile * LPW + l;
+    const int nx = I.nx, ny = I.ny;
+    const int nlines = DIR == 0 ? (ny + 1) / 2 : nx / 2;
+    const bool active = line < nlines;
+    cpx<T>* lds = lds_all + l * N;
+    T* fld = reinterpret_cast<T*>(I.base);
+    const int64_t nc = I.ncell;
+    const T* __restrict__ kap = reinterpret_cast<const T*>(DIR == 0 ? I.kx : I.ky);
+    const cpx<T>* __restrict__ tw = reinterpret_cast<const cpx<T>*>(DIR == 0 ? I.twx : I.twy);
+
+    cpx<T> X0[R], X1[R];
+    load_line<T, DIR, R, TPL>(fld + J.in[0] * nc, X0, line, t, nx, ny, active);
+    LineFFT<T, N, R, false>::run(X0, lds, t, tw);
+    const bool two = J.in[1] >= 0;
+    if (two) {
+        load_line<T, DIR, R, TPL>(fld + J.in[1] * nc, X1, line, t, nx, ny, active);
+        LineFFT<T, N, R, false>::run(X1, lds, t, tw);
+    }
+    const T invN = T(1.0 / N);
+#pragma unroll
+    for (int o = 0; o < 2; ++o) {
+        if (J.out[o] < 0) continue;
+        cpx<T> Y[R];
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            const int k = t + m * TPL;
+            const T kk = kap[k];
+            cpx<T> y = {T(0), T(0)};
+#pragma unroll
+            for (int s = 0; s < 2; ++s) {
+                const int mk = J.mult[o][s];
+                if (s == 1 && !two) continue;
+                const cpx<T> x = s == 0 ? X0[m] : X1[m];
+                if (mk == M_D) {          // i k / N
+                    const T a = kk * invN;
+                    y.re -= a * x.im;
+                    y.im += a * x.re;
+                } else if (mk == M_DD) {  // -k^2 / N
+                    const T a = -kk * kk * invN;
+                    y.re += a * x.re;
+                    y.im += a * x.im;
+                }
+            }
+            Y[m] = y;
+        }
+        LineFFT<T, N, R, true>::run(Y, lds, t, tw);
+        if (!active) continue;
+        const int pre = J.pre[o], post = J.post[o], sc = J.scale[o];
+        T* __restrict__ out = fld + J.out[o] * nc;
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            const int p = t + m * TPL;
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                if (DIR == 0 && h == 1 && 2 * line + 1 >= ny) continue;
+                const int64_t e = h == 0 ? LineAddr<DIR>::re(line, p, nx) : LineAddr<DIR>::im(line, p, nx);
+                T val = h == 0 ? Y[m].re : Y[m].im;
+                if (pre >= 0) val += fld[pre * nc + e];
+                if (sc != S_ONE) {
+                    const T rho = fld[RHO * nc + e], T_ = fld[TT * nc + e];
+                    val = sc == S_INV_RHOT ? val / (rho * T_) : val / (rho * T_ * T_);
+                }
+                if (post >= 0) val += fld[post * nc + e];
+                out[e] = val;
+            }
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Equilibrium f_i^eq of the seven kinetic moments: f^eq = C^{-1} M^eq(rho, u, T).
+template <typename T>
+__device__ __forceinline__ T feq_pop(const DvmConst<T>& D, int i, T rho, T ux, T uy, T Tm, T b) {
+    const T u2 = ux * ux + uy * uy;
+    const T h2 = (b + T(2)) * Tm + u2;
+    const T h4 = (b + T(4)) * Tm + u2;
+    const T m[16] = {T(1), ux, uy, b * Tm + u2,
+                     Tm + ux * ux, ux * uy, Tm + uy * uy,
+                     ux * h2, uy * h2,
+                     T(3) * Tm * ux + ux * ux * ux, Tm * uy + ux * ux * uy,
+                     Tm * ux + ux * uy * uy, T(3) * Tm * uy + uy * uy * uy,
+                     h2 * Tm + h4 * ux * ux, h4 * ux * uy, h2 * Tm + h4 * uy * uy};
+    T s = T(0);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) s += D.cinv[i][j] * m[j];
+    return rho * s;
+}
+
+// ---------------------------------------------------------------------------------------
+// Population x pass: one block = (instance, tile of row pairs, population i).
+//   partial = base + c [ -v_x D_x f - (f - f^eq)/tau + I ]          (written to F_P + i)
+//   axis-x populations (v_y = 0) are final and go to out_field + i.
+template <typename T, int N>
+__global__ void __launch_bounds__((LineCfg<T, N, 0>::WG))
+pop_x_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, int ngroups,
+           int ntiles, const DvmConst<T>* __restrict__ dvm, StageArgs st) {
+    using C = LineCfg<T, N, 0>;
+    constexpr int R = C::R, TPL = C::TPL;
+    __shared__ cpx<T> lds_all[C::LDS];
+    const BlockWork w = decode_block(ngroups, ntiles, 16);
+    if (!w.valid) return;
+    const InstDesc& I = insts[ilist[w.inst_local]];
+    const DvmConst<T>& D = *dvm;
+    const int i = w.job;
+    const int tid = threadIdx.x;
+    const int l = tid / TPL, t = tid % TPL;
+    const int line = w.tile * C::LPW + l;
+    const int nx = I.nx, ny = I.ny;
+    const bool active = line < (ny + 1) / 2;
+    cpx<T>* lds = lds_all + l * N;
+    T* fld = reinterpret_cast<T*>(I.base);
+    const int64_t nc = I.ncell;
+    const T vx = D.vx[i], vy = D.vy[i];
+    const T c = T(st.use_dt ? st.alpha * I.dt : st.alpha);
+
+    cpx<T> F[R], X[R];
+    load_line<T, 0, R, TPL>(fld + (st.f_field + i) * nc, F, line, t, nx, ny, active);
+    if (vx != T(0)) {
+#pragma unroll
+        for (int m = 0; m < R; ++m) X[m] = F[m];
+        LineFFT<T, N, R, false>::run(X, lds, t, reinterpret_cast<const cpx<T>*>(I.twx));
+        const T* __restrict__ kap = reinterpret_cast<const T*>(I.kx);
+        const T s = -c * vx * T(1.0 / N);
+#pragma unroll
+        for (int m = 0; m < R; ++m) {
+            const T a = s * kap[t + m * TPL];
+            const cpx<T> x = X[m];
+            X[m] = {-a * x.im, a * x.re};
+        }
+        LineFFT<T, N, R, true>::run(X, lds, t, reinterpret_cast<const cpx<T>*>(I.twx));
+    } else {
+#pragma unroll
+        for (int m = 0; m < R; ++m) X[m] = {T(0), T(0)};
+    }
+    if (!active) return;
+    const T inv_tau = T(1.0 / I.tau), b = T(I.b);
+    const int ct = I.q != 0.0 ? CT : C0;
+    const bool final_here = (vy == T(0));
+    // out may equal the base block (second stage writes f^{n+1} over f^n cell by cell): no restrict
+    T* out = fld + ((final_here ? st.out_field : F_P) + i) * nc;
+    const T* basep = st.base_field >= 0 ? fld + (st.base_field + i) * nc : nullptr;
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        const int p = t + m * TPL;
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            if (h == 1 && 2 * line + 1 >= ny) continue;
+            const int64_t e = (int64_t)(2 * line + h) * nx + p;
+            const T rho = fld[RHO * nc + e], ux = fld[UX * nc + e], uy = fld[UY * nc + e];
+            const T Tm = fld[TT * nc + e];
+            const T Bx = fld[BX * nc + e], By = fld[BY * nc + e], Dc = fld[ct * nc + e];
+            const T fv = h == 0 ? F[m].re : F[m].im;
+            const T dv = h == 0 ? X[m].re : X[m].im;
+            const T fe = feq_pop(D, i, rho, ux, uy, Tm, b);
+            const T cx = vx - ux, cy = vy - uy;
+            const T A = T(-2) * Dc * Tm;
+            const T force = -(A + Bx * cx + By * cy + Dc * (cx * cx + cy * cy)) * fe;
+            const T base = basep ? basep[e] : T(0);
+            out[e] = base + dv + c * (force - (fv - fe) * inv_tau);
+        }
+    }
+}
+
+// Population y pass: one block = (instance, tile of column pairs, population i with v_y != 0).
+//   out = partial - c v_y D_y f
+template <typename T, int N>
+__global__ void __launch_bounds__((LineCfg<T, N, 1>::WG))
+pop_y_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, int ngroups,
+           int ntiles, const DvmConst<T>* __restrict__ dvm, const int* __restrict__ pops, int npops,
+           StageArgs st) {
+    using C = LineCfg<T, N, 1>;
+    constexpr int R = C::R, TPL = C::TPL, LPW = C::LPW;
+    __shared__ cpx<T> lds_all[C::LDS];
+    const BlockWork w = decode_block(ngroups, ntiles, npops);
+    if (!w.valid) return;
+    const InstDesc& I = insts[ilist[w.inst_local]];
+    const int i = pops[w.job];
+    const int tid = threadIdx.x;
+    const int l = tid % LPW, t = tid / LPW;
+    const int line = w.tile * LPW + l;
+    const int nx = I.nx, ny = I.ny;
+    const bool active = line < nx / 2;
+    cpx<T>* lds = lds_all + l * N;
+    T* fld = reinterpret_cast<T*>(I.base);
+    const int64_t nc = I.ncell;
+    const T vy = dvm->vy[i];
+
+    cpx<T> X[R];
+    load_line<T, 1, R, TPL>(fld + (st.f_field + i) * nc, X, line, t, nx, ny, active);
+    LineFFT<T, N, R, false>::run(X, lds, t, reinterpret_cast<const cpx<T>*>(I.twy));
+    const T* __restrict__ kap = reinterpret_cast<const T*>(I.ky);
+    const T s = -T(st.use_dt ? st.alpha * I.dt : st.alpha) * vy * T(1.0 / N);
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        const T a = s * kap[t + m * TPL];
+        const cpx<T> x = X[m];
+        X[m] = {-a * x.im, a * x.re};
+    }
+    LineFFT<T, N, R, true>::run(X, lds, t, reinterpret_cast<const cpx<T>*>(I.twy));
+    if (!active) return;
+    const T* __restrict__ part = fld + (F_P + i) * nc;
+    T* __restrict__ out = fld + (st.out_field + i) * nc;
+#pragma unroll
+    for (int m = 0; m < R; ++m) {
+        const int p = t + m * TPL;
+        const int64_t e = LineAddr<1>::re(line, p, nx);
+        const vec2<T> pv = *reinterpret_cast<const vec2<T>*>(part + e);
+        vec2<T> o;
+        o.a = pv.a + X[m].re;
+        o.b = pv.b + X[m].im;
+        *reinterpret_cast<vec2<T>*>(out + e) = o;
+    }
+}
+
+// ---------------------------------------------------------------------------------------
+// Pointwise kernels: grid = (cell chunks, instances in the launch).
+#define LB_POINTWISE_PROLOGUE                                       \
+    const InstDesc& I = insts[ilist[blockIdx.y]];                   \
+    const int64_t nc = I.ncell;                                     \
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; \
+    if (e >= nc) return;                                            \
+    T* fld = reinterpret_cast<T*>(I.base);
+
+// Moments of Sec. 2.1: rho = sum f, rho u = sum f v, rho (b T + u^2) = sum f (v^2 + eta^2).
+template <typename T>
+__global__ void __launch_bounds__(256)
+moments_kernel(const InstDesc* __restrict__ insts, const int* __restrict__ ilist,
+               const DvmConst<T>* __restrict__ dvm, int f_field) {
+    LB_POINTWISE_PROLOGUE
+    const DvmConst<T>& D = *dvm;
+    T r = 0, jx = 0, jy = 0, en = 0;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const T f = fld[(f_field + i) * nc + e];
+        r += f;
+        jx += f * D.vx[i];
+        jy += f * D.vy[i];
+        en += f * D.w[i];
+    }
+    const T ux = jx / r, uy = jy / r;
+    fld[RHO * nc + e] = r;
+    fld[UX * nc + e] = ux;
+    fld[UY * nc + e] = uy;
+    fld[TT * nc + e] = (en / r - ux * ux - uy * uy) / T(I.b);
+}
+
+// Stress S = (P^w - rho T) I + Lambda - zeta (div u) I, the C of Eq. (2) without C_q, and
+// Q = q rho T grad T (Sec. 2.2).
+template <typename T>
+__global__ void __launch_bounds__(256)
+stress_kernel(const InstDesc* __restrict__ insts, const int* __restrict__ ilist) {
+    LB_POINTWISE_PROLOGUE
+    const T rho = fld[RHO * nc + e], Tm = fld[TT * nc + e];
+    const T rx = fld[RX * nc + e], ry = fld[RY * nc + e], lap = fld[LAP * nc + e];
+    const T Tx = fld[TX * nc + e], Ty = fld[TY * nc + e];
+    const T uxx = fld[UXX * nc + e], uxy = fld[UXY * nc + e];   // d_x u_x, d_y u_x
+    const T uyx = fld[UYX * nc + e], uyy = fld[UYY * nc + e];   // d_x u_y, d_y u_y
+    const T gdx = fld[GDX * nc + e], gdy = fld[GDY * nc + e];
+    const T K = T(I.K), H = T(I.H), zeta = T(I.zeta), a = T(I.a), bw = T(I.bw);
+
+    const T div = uxx + uyy;
+    const T rT = rho * Tm;
+    const T Pw = rT / (T(1) - bw * rho) - a * rho * rho;
+    const T M = K + H * Tm;
+    const T g2 = rx * rx + ry * ry;
+    const T iT2 = T(1) / (Tm * Tm);
+    const T mtx = -K * Tx * iT2, mty = -K * Ty * iT2;   // grad(M/T), H constant
+    const T iso = -M * (rho * lap + T(0.5) * g2) - rT * (rx * mtx + ry * mty);
+    const T Lxx = M * rx * rx + iso, Lxy = M * rx * ry, Lyy = M * ry * ry + iso;
+    const T pn = Pw - rT;
+    fld[SXX * nc + e] = pn + Lxx - zeta * div;
+    fld[SXY * nc + e] = Lxy;
+    fld[SYY * nc + e] = pn + Lyy - zeta * div;
+    const T lam_du = Lxx * uxx + Lxy * uyx + Lxy * uxy + Lyy * uyy;
+    const T rgr = rx * (uxx * rx + uyx * ry) + ry * (uxy * rx + uyy * ry);
+    const T num = pn * div + lam_du - zeta * div * div + a * rho * rho * div +
+                  K * (T(-0.5) * g2 * div - rho * (rx * gdx + ry * gdy) - rgr);
+    fld[C0 * nc + e] = num / (T(2) * rT * Tm);
+    if (I.q != 0.0) {
+        const T qrt = T(I.q) * rT;
+        fld[QX * nc + e] = qrt * Tx;
+        fld[QY * nc + e] = qrt * Ty;
+    }
+}
+
+// Initial populations f = f^eq(rho0, u0, T0), computed in float64 from float64 inputs staged in
+// the F_B block (4 double fields), stored in the working precision into F_A.
+template <typename T>
+__global__ void __launch_bounds__(256)
+init_kernel(const InstDesc* __restrict__ insts, const int* __restrict__ ilist,
+            const DvmConst<double>* __restrict__ dvm) {
+    LB_POINTWISE_PROLOGUE
+    const double* stage = reinterpret_cast<const double*>(fld + F_B * nc);
+    const double rho = stage[e], ux = stage[nc + e], uy = stage[2 * nc + e], Tm = stage[3 * nc + e];
+    double f[16];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) f[i] = feq_pop<double>(*dvm, i, rho, ux, uy, Tm, I.b);
+#pragma unroll
+    for (int i = 0; i < 16; ++i) fld[(F_A + i) * nc + e] = T(f[i]);
+}
+
+// Per-cell conserved densities, summed per block in float64:
+//   mass rho, momentum rho u, energy rho (b T + u^2)/2 - a rho^2 + K |grad rho|^2 / 2.
+// Block partial sums are written to red[blockIdx.x * 5 + k]; k = 4 counts non-finite cells.
+template <typename T>
+__global__ void __launch_bounds__(256)
+conserve_partial(const InstDesc* __restrict__ insts, int inst) {
+    const InstDesc& I = insts[inst];
+    const int64_t nc = I.ncell;
+    const T* fld = reinterpret_cast<const T*>(I.base);
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nc;
+         e += (int64_t)gridDim.x * blockDim.x) {
+        const double rho = fld[RHO * nc + e], ux = fld[UX * nc + e], uy = fld[UY * nc + e];
+        const double Tm = fld[TT * nc + e], rx = fld[RX * nc + e], ry = fld[RY * nc + e];
+        const double en = 0.5 * rho * (I.b * Tm + ux * ux + uy * uy) - I.a * rho * rho +
+                          0.5 * I.K * (rx * rx + ry * ry);
+        acc[0] += rho;
+        acc[1] += rho * ux;
+        acc[2] += rho * uy;
+        acc[3] += en;
+        acc[4] += (isfinite(rho) && isfinite(ux) && isfinite(uy) && isfinite(Tm)) ? 0.0 : 1.0;
+    }
+    __shared__ double sh[5][256];
+#pragma unroll
+    for (int k = 0; k < 5; ++k) sh[k][threadIdx.x] = acc[k];
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if ((int)threadIdx.x < s) {
+#pragma unroll
+            for (int k = 0; k < 5; ++k) sh[k][threadIdx.x] += sh[k][threadIdx.x + s];
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) I.red[blockIdx.x * 5 + k] = sh[k][0];
+    }
+}
+
+// Convert between the working precision and float64 (host transfers of non-hot calls).
+template <typename T>
+__global__ void __launch_bounds__(256) to_f64(const T* __restrict__ src, double* __restrict__ dst, int64_t n) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) dst[e] = double(src[e]);
+}
+template <typename T>
+__global__ void __launch_bounds__(256) from_f64(const double* __restrict__ src, T* __restrict__ dst, int64_t n) {
+    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e < n) dst[e] = T(src[e]);
+}
+
+}  // namespace lbfft

@@ -1,0 +1,45 @@
+// Internal launch interface between the host runtime and the kernel units.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "lb_types.h"
+
+namespace lbfft {
+
+// One launch covers `ninst` instances of the same grid size, listed (as indices into `insts`)
+// in device array `ilist`.
+struct LaunchSet {
+    const InstDesc* insts;
+    const int* ilist;
+    int ninst;
+    int nx, ny;
+    hipStream_t stream;
+};
+
+// Line passes (lb_lines_<dir>_<prec>.hip).
+hipError_t macro_x_f64(const LaunchSet& L, const JobDesc* jobs, int njobs);
+hipError_t macro_y_f64(const LaunchSet& L, const JobDesc* jobs, int njobs);
+hipError_t macro_x_f32(const LaunchSet& L, const JobDesc* jobs, int njobs);
+hipError_t macro_y_f32(const LaunchSet& L, const JobDesc* jobs, int njobs);
+hipError_t pop_x_f64(const LaunchSet& L, const DvmConst<double>* dvm, const int* pops, int npops, StageArgs st);
+hipError_t pop_y_f64(const LaunchSet& L, const DvmConst<double>* dvm, const int* pops, int npops, StageArgs st);
+hipError_t pop_x_f32(const LaunchSet& L, const DvmConst<float>* dvm, const int* pops, int npops, StageArgs st);
+hipError_t pop_y_f32(const LaunchSet& L, const DvmConst<float>* dvm, const int* pops, int npops, StageArgs st);
+
+// Pointwise kernels (lb_pointwise.hip).
+template <typename T>
+hipError_t launch_moments(const LaunchSet& L, const DvmConst<T>* dvm, int f_field);
+template <typename T>
+hipError_t launch_stress(const LaunchSet& L);
+template <typename T>
+hipError_t launch_init(const LaunchSet& L, const DvmConst<double>* dvm);
+template <typename T>
+hipError_t launch_tables(const InstDesc* insts, int inst, int nx, int ny, hipStream_t s);
+template <typename T>
+hipError_t launch_conserve(const InstDesc* insts, int inst, int nblocks, hipStream_t s);
+template <typename T>
+hipError_t launch_to_f64(const void* src, double* dst, int64_t n, hipStream_t s);
+template <typename T>
+hipError_t launch_from_f64(const double* src, void* dst, int64_t n, hipStream_t s);
+
+}  // namespace lbfft

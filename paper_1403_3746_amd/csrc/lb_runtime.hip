@@ -1,0 +1,708 @@
+// Host runtime of the lbfft C ABI: argument checks, workspace carving, float64 tables and the
+// inverse moment matrix, stage sequencing, HIP graph capture of one Runge-Kutta step, and the
+// synchronising diagnostics.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/lbfft.h"
+#include "lb_launch.h"
+#include "lb_types.h"
+
+using namespace lbfft;
+
+namespace {
+
+thread_local std::string g_err;
+
+lb_status fail(lb_status s, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return s;
+}
+
+#define LB_HIP(call)                                                                         \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(LB_E_HIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),    \
+                        __FILE__, __LINE__);                                                 \
+    } while (0)
+
+constexpr size_t ALIGN = 256;
+inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+bool line_ok(int n) {
+    static const int sizes[] = {8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768,
+                                1024, 1536, 2048};
+    for (int s : sizes)
+        if (s == n) return true;
+    return false;
+}
+
+bool grid_ok(int nx, int ny) { return line_ok(nx) && (line_ok(ny) || ny == 1 || ny == 2); }
+
+size_t word_bytes(lb_precision p) { return p == LB_FP64 ? 8 : 4; }
+
+// Conservation partial sums: at most this many blocks, 5 doubles each.
+constexpr int RED_BLOCKS = 1024;
+
+// Workspace layout.  Header: InstDesc[n], DvmConst<double>, DvmConst<float>, job tables,
+// population list, instance index lists, reduction partials.  Then per instance: tables
+// (kx, ky, twx, twy) and the field arena.
+struct Layout {
+    size_t insts, dvm64, dvm32, jobs, pops, ilist, red, header;
+    std::vector<size_t> tables, arena;
+    size_t total;
+};
+
+constexpr int MAX_JOBS = 32;
+
+Layout make_layout(int n, const lb_params* p, lb_precision prec) {
+    Layout L;
+    size_t off = 0;
+    L.insts = off; off = align_up(off + sizeof(InstDesc) * n);
+    L.dvm64 = off; off = align_up(off + sizeof(DvmConst<double>));
+    L.dvm32 = off; off = align_up(off + sizeof(DvmConst<float>));
+    L.jobs = off;  off = align_up(off + sizeof(JobDesc) * MAX_JOBS);
+    L.pops = off;  off = align_up(off + sizeof(int) * 16);
+    L.ilist = off; off = align_up(off + sizeof(int) * 2 * n);
+    L.red = off;   off = align_up(off + sizeof(double) * 5 * RED_BLOCKS);
+    L.header = off;
+    const size_t w = word_bytes(prec);
+    for (int k = 0; k < n; ++k) {
+        const size_t nc = (size_t)p[k].nx * p[k].ny;
+        L.tables.push_back(off);
+        off = align_up(off + w * (p[k].nx + p[k].ny) + 2 * w * (p[k].nx + p[k].ny) + 4 * ALIGN);
+        L.arena.push_back(off);
+        off = align_up(off + w * nc * NFIELDS);
+    }
+    L.total = off;
+    return L;
+}
+
+// Gauss-Jordan inverse with partial pivoting (float64).  Returns false if singular.
+bool invert16(const double A[16][16], double X[16][16]) {
+    double M[16][32];
+    for (int i = 0; i < 16; ++i)
+        for (int j = 0; j < 32; ++j) M[i][j] = j < 16 ? A[i][j] : (j - 16 == i ? 1.0 : 0.0);
+    for (int c = 0; c < 16; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < 16; ++r)
+            if (std::fabs(M[r][c]) > std::fabs(M[piv][c])) piv = r;
+        if (std::fabs(M[piv][c]) < 1e-300) return false;
+        if (piv != c)
+            for (int j = 0; j < 32; ++j) std::swap(M[c][j], M[piv][j]);
+        const double d = M[c][c];
+        for (int j = 0; j < 32; ++j) M[c][j] /= d;
+        for (int r = 0; r < 16; ++r) {
+            if (r == c) continue;
+            const double f = M[r][c];
+            if (f == 0.0) continue;
+            for (int j = 0; j < 32; ++j) M[r][j] -= f * M[c][j];
+        }
+    }
+    for (int i = 0; i < 16; ++i)
+        for (int j = 0; j < 16; ++j) X[i][j] = M[i][16 + j];
+    return true;
+}
+
+// D2V16 velocities (population order of the header) and the inverse of the moment matrix whose
+// rows are the seven kinetic moments [1, vx, vy, w, vx^2, vx vy, vy^2, w vx, w vy, vx^3,
+// vx^2 vy, vx vy^2, vy^3, w vx^2, w vx vy, w vy^2], w = v^2 + eta^2 (Sec. 2.1, 2.2).
+bool build_dvm(const lb_dvm& d, DvmConst<double>& D) {
+    const double ax[4][2] = {{1, 0}, {0, 1}, {-1, 0}, {0, -1}};
+    const double dg[4][2] = {{1, 1}, {-1, 1}, {-1, -1}, {1, -1}};
+    const double speed[4] = {d.va, d.vb, d.vc, d.vd};
+    for (int ring = 0; ring < 4; ++ring)
+        for (int k = 0; k < 4; ++k) {
+            const int i = ring * 4 + k;
+            const double(*u)[2] = (ring % 2 == 0) ? ax : dg;
+            D.vx[i] = speed[ring] * u[k][0];
+            D.vy[i] = speed[ring] * u[k][1];
+            const double eta = ring == 0 ? d.eta0 : 0.0;
+            D.w[i] = D.vx[i] * D.vx[i] + D.vy[i] * D.vy[i] + eta * eta;
+        }
+    double A[16][16];
+    for (int i = 0; i < 16; ++i) {
+        const double x = D.vx[i], y = D.vy[i], w = D.w[i];
+        const double row[16] = {1, x, y, w, x * x, x * y, y * y, w * x, w * y,
+                                x * x * x, x * x * y, x * y * y, y * y * y,
+                                w * x * x, w * x * y, w * y * y};
+        for (int j = 0; j < 16; ++j) A[j][i] = row[j];
+    }
+    return invert16(A, D.cinv);
+}
+
+}  // namespace
+
+struct lb_ctx {
+    int n = 0;
+    lb_precision prec = LB_FP64;
+    std::vector<lb_params> p;
+    lb_dvm dvm{};
+    unsigned char* ws = nullptr;
+    size_t ws_bytes = 0;
+    hipStream_t stream = nullptr;
+    Layout lay;
+    std::vector<InstDesc> hinst;
+    // host copies uploaded at init (kept alive for the asynchronous copies)
+    DvmConst<double> dvm64{};
+    DvmConst<float> dvm32{};
+    std::vector<JobDesc> jobs;
+    std::vector<int> ilist_h;
+    int pops_h[16] = {0};
+    int npops = 0;
+    // job table slices
+    int j_x1 = 0, n_x1 = 0, j_y1 = 0, n_y1 = 0, j_x2 = 0, n_x2 = 0, j_y2 = 0, n_y2 = 0;
+    int j_dx = 0, j_dxx = 0, j_dy = 0, j_dyy = 0;   // single-job tables of lb_derivative
+    // size classes: instances sharing (nx, ny), as a slice [start, start+count) of ilist
+    struct Class {
+        int nx, ny, start, count;
+    };
+    std::vector<Class> classes;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    bool use_graph = true;
+
+    template <typename Q>
+    Q* dev(size_t off) const { return reinterpret_cast<Q*>(ws + off); }
+    const InstDesc* d_insts() const { return dev<InstDesc>(lay.insts); }
+    const JobDesc* d_jobs(int j) const { return dev<JobDesc>(lay.jobs) + j; }
+    const int* d_ilist(int k) const { return dev<int>(lay.ilist) + k; }
+    size_t wbytes() const { return word_bytes(prec); }
+};
+
+namespace {
+
+JobDesc job(int in0, int out0, int m0, int out1 = -1, int m1 = M_NONE) {
+    JobDesc j;
+    std::memset(&j, 0, sizeof(j));
+    j.in[0] = (int16_t)in0;
+    j.in[1] = -1;
+    j.out[0] = (int16_t)out0;
+    j.out[1] = (int16_t)out1;
+    j.pre[0] = j.pre[1] = j.post[0] = j.post[1] = -1;
+    j.mult[0][0] = (int8_t)m0;
+    j.mult[1][0] = (int8_t)m1;
+    j.mult[0][1] = j.mult[1][1] = M_NONE;
+    j.scale[0] = j.scale[1] = S_ONE;
+    return j;
+}
+
+// Job tables of the four macroscopic line passes of one stage.
+void build_jobs(lb_ctx& c) {
+    auto& J = c.jobs;
+    J.clear();
+    // X1: d_x, d_xx of rho; d_x T; d_x, d_xx of u_x; d_x u_y
+    c.j_x1 = (int)J.size();
+    J.push_back(job(RHO, RX, M_D, RXX, M_DD));
+    J.push_back(job(TT, TX, M_D));
+    J.push_back(job(UX, UXX, M_D, UXXX, M_DD));
+    J.push_back(job(UY, UYX, M_D));
+    c.n_x1 = (int)J.size() - c.j_x1;
+    // Y1: d_y rho, lap rho = d_xx rho + d_yy rho, d_y T, d_y u_x, d_y u_y,
+    //     d_x(div u) = d_xx u_x + d_y (d_x u_y), d_y(div u) = d_y (d_x u_x) + d_yy u_y
+    c.j_y1 = (int)J.size();
+    {
+        JobDesc j = job(RHO, RY, M_D, LAP, M_DD);
+        j.pre[1] = RXX;
+        J.push_back(j);
+    }
+    J.push_back(job(TT, TY, M_D));
+    J.push_back(job(UX, UXY, M_D));
+    J.push_back(job(UY, UYY, M_D));
+    {
+        JobDesc j = job(UYX, GDX, M_D);
+        j.pre[0] = UXXX;
+        J.push_back(j);
+    }
+    {
+        JobDesc j = job(UXX, GDY, M_D);
+        j.in[1] = UY;
+        j.mult[0][1] = M_DD;
+        J.push_back(j);
+    }
+    c.n_y1 = (int)J.size() - c.j_y1;
+    // X2: d_x S_xx, d_x S_xy, d_x Q_x (q != 0 only)
+    c.j_x2 = (int)J.size();
+    J.push_back(job(SXX, DSXX, M_D));
+    J.push_back(job(SXY, DSXY, M_D));
+    {
+        JobDesc j = job(QX, DQX, M_D);
+        j.flag_q = 1;
+        J.push_back(j);
+    }
+    c.n_x2 = (int)J.size() - c.j_x2;
+    // Y2: B = div S / (rho T);  C + C_q = C0 + div Q / (rho T^2)
+    c.j_y2 = (int)J.size();
+    {
+        JobDesc j = job(SXY, BX, M_D);
+        j.pre[0] = DSXX;
+        j.scale[0] = S_INV_RHOT;
+        J.push_back(j);
+    }
+    {
+        JobDesc j = job(SYY, BY, M_D);
+        j.pre[0] = DSXY;
+        j.scale[0] = S_INV_RHOT;
+        J.push_back(j);
+    }
+    {
+        JobDesc j = job(QY, CT, M_D);
+        j.pre[0] = DQX;
+        j.scale[0] = S_INV_RHOT2;
+        j.post[0] = C0;
+        j.flag_q = 1;
+        J.push_back(j);
+    }
+    c.n_y2 = (int)J.size() - c.j_y2;
+    // lb_derivative: SCR0 -> SCR1
+    c.j_dx = (int)J.size();
+    J.push_back(job(SCR0, SCR1, M_D));
+    c.j_dxx = (int)J.size();
+    J.push_back(job(SCR0, SCR1, M_DD));
+    c.j_dy = c.j_dx;
+    c.j_dyy = c.j_dxx;
+}
+
+LaunchSet set_of(const lb_ctx& c, const lb_ctx::Class& k) {
+    return LaunchSet{c.d_insts(), c.d_ilist(k.start), k.count, k.nx, k.ny, c.stream};
+}
+
+LaunchSet set_one(const lb_ctx& c, int inst, hipStream_t s) {
+    // the second half of ilist is the identity map
+    return LaunchSet{c.d_insts(), c.d_ilist(c.n + inst), 1, c.p[inst].nx, c.p[inst].ny, s};
+}
+
+hipError_t macro(const lb_ctx& c, const LaunchSet& L, int dir, int j0, int nj) {
+    const JobDesc* jt = c.d_jobs(j0);
+    if (c.prec == LB_FP64) return dir == 0 ? macro_x_f64(L, jt, nj) : macro_y_f64(L, jt, nj);
+    return dir == 0 ? macro_x_f32(L, jt, nj) : macro_y_f32(L, jt, nj);
+}
+
+hipError_t moments(const lb_ctx& c, const LaunchSet& L, int f_field) {
+    if (c.prec == LB_FP64) return launch_moments<double>(L, c.dev<DvmConst<double>>(c.lay.dvm64), f_field);
+    return launch_moments<float>(L, c.dev<DvmConst<float>>(c.lay.dvm32), f_field);
+}
+
+hipError_t stress(const lb_ctx& c, const LaunchSet& L) {
+    return c.prec == LB_FP64 ? launch_stress<double>(L) : launch_stress<float>(L);
+}
+
+// Moments and the force coefficients B, C (+ C_q) of the population block f_field.
+hipError_t force_passes(const lb_ctx& c, const LaunchSet& L, int f_field) {
+    hipError_t e;
+    if ((e = moments(c, L, f_field)) != hipSuccess) return e;
+    if ((e = macro(c, L, 0, c.j_x1, c.n_x1)) != hipSuccess) return e;
+    if ((e = macro(c, L, 1, c.j_y1, c.n_y1)) != hipSuccess) return e;
+    if ((e = stress(c, L)) != hipSuccess) return e;
+    if ((e = macro(c, L, 0, c.j_x2, c.n_x2)) != hipSuccess) return e;
+    return macro(c, L, 1, c.j_y2, c.n_y2);
+}
+
+hipError_t pop_passes(const lb_ctx& c, const LaunchSet& L, StageArgs st) {
+    hipError_t e;
+    const int* pops = c.dev<int>(c.lay.pops);
+    if (c.prec == LB_FP64) {
+        const auto* d = c.dev<DvmConst<double>>(c.lay.dvm64);
+        if ((e = pop_x_f64(L, d, pops, c.npops, st)) != hipSuccess) return e;
+        return pop_y_f64(L, d, pops, c.npops, st);
+    }
+    const auto* d = c.dev<DvmConst<float>>(c.lay.dvm32);
+    if ((e = pop_x_f32(L, d, pops, c.npops, st)) != hipSuccess) return e;
+    return pop_y_f32(L, d, pops, c.npops, st);
+}
+
+// One Runge-Kutta stage of every instance on stream s.
+hipError_t enqueue_stage(const lb_ctx& c, hipStream_t s, StageArgs st) {
+    hipError_t e;
+    for (const auto& k : c.classes) {
+        LaunchSet L = set_of(c, k);
+        L.stream = s;
+        if ((e = force_passes(c, L, st.f_field)) != hipSuccess) return e;
+        if ((e = pop_passes(c, L, st)) != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// f^{n+1/2} = f^n + dt/2 R(f^n) into F_B;  f^{n+1} = f^n + dt R(f^{n+1/2}) into F_A.
+hipError_t enqueue_step(const lb_ctx& c, hipStream_t s) {
+    StageArgs s1{F_A, F_A, F_B, 0.5, 1};
+    StageArgs s2{F_B, F_A, F_A, 1.0, 1};
+    hipError_t e = enqueue_stage(c, s, s1);
+    if (e != hipSuccess) return e;
+    return enqueue_stage(c, s, s2);
+}
+
+lb_status check_inst(const lb_ctx* c, int inst) {
+    if (!c) return fail(LB_E_ARG, "null context");
+    if (inst < 0 || inst >= c->n) return fail(LB_E_ARG, "instance %d out of range [0,%d)", inst, c->n);
+    return LB_OK;
+}
+
+// Copy field `fid` of instance inst (nc words of the working precision) to host float64.
+lb_status field_to_host(lb_ctx* c, int inst, int fid, double* dst, int64_t nfields = 1) {
+    const InstDesc& I = c->hinst[inst];
+    const int64_t n = I.ncell * nfields;
+    unsigned char* src = reinterpret_cast<unsigned char*>(I.base) + (size_t)fid * I.ncell * c->wbytes();
+    if (c->prec == LB_FP64) {
+        LB_HIP(hipMemcpyAsync(dst, src, n * 8, hipMemcpyDeviceToHost, c->stream));
+        LB_HIP(hipStreamSynchronize(c->stream));
+    } else {
+        std::vector<float> tmp(n);
+        LB_HIP(hipMemcpyAsync(tmp.data(), src, n * 4, hipMemcpyDeviceToHost, c->stream));
+        LB_HIP(hipStreamSynchronize(c->stream));
+        for (int64_t k = 0; k < n; ++k) dst[k] = tmp[k];
+    }
+    return LB_OK;
+}
+
+lb_status field_from_host(lb_ctx* c, int inst, int fid, const double* src, int64_t nfields = 1) {
+    const InstDesc& I = c->hinst[inst];
+    const int64_t n = I.ncell * nfields;
+    unsigned char* dst = reinterpret_cast<unsigned char*>(I.base) + (size_t)fid * I.ncell * c->wbytes();
+    if (c->prec == LB_FP64) {
+        LB_HIP(hipMemcpyAsync(dst, src, n * 8, hipMemcpyHostToDevice, c->stream));
+        LB_HIP(hipStreamSynchronize(c->stream));
+    } else {
+        std::vector<float> tmp(n);
+        for (int64_t k = 0; k < n; ++k) tmp[k] = (float)src[k];
+        LB_HIP(hipMemcpyAsync(dst, tmp.data(), n * 4, hipMemcpyHostToDevice, c->stream));
+        LB_HIP(hipStreamSynchronize(c->stream));
+    }
+    return LB_OK;
+}
+
+lb_status validate_params(const lb_params& q, int k) {
+    if (!grid_ok(q.nx, q.ny))
+        return fail(LB_E_SIZE, "instance %d: unsupported grid %dx%d (each side 2^a or 3*2^a in "
+                    "[8,2048]; ny may also be 1 or 2)", k, q.nx, q.ny);
+    if (!(q.dx > 0) || !(q.dt > 0) || !(q.tau > 0) || !(q.b_dof > 0))
+        return fail(LB_E_ARG, "instance %d: dx, dt, tau and b must be positive", k);
+    const double v[] = {q.K, q.H, q.zeta, q.q, q.vdw_a, q.vdw_b};
+    for (double x : v)
+        if (!std::isfinite(x)) return fail(LB_E_ARG, "instance %d: non-finite parameter", k);
+    if (q.vdw_b < 0) return fail(LB_E_ARG, "instance %d: vdw_b must be >= 0", k);
+    return LB_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* lb_last_error(void) { return g_err.c_str(); }
+
+size_t lb_workspace_bytes(int n_inst, const lb_params* p, lb_precision prec) {
+    if (n_inst <= 0 || !p || (prec != LB_FP64 && prec != LB_FP32)) return 0;
+    for (int k = 0; k < n_inst; ++k)
+        if (validate_params(p[k], k) != LB_OK) return 0;
+    return make_layout(n_inst, p, prec).total;
+}
+
+lb_status lb_init(lb_ctx** out, int n_inst, const lb_params* p, const lb_dvm* dvm,
+                  lb_precision prec, const double* const* rho0, const double* const* ux0,
+                  const double* const* uy0, const double* const* T0, void* d_workspace,
+                  size_t ws_bytes, void* hip_stream) {
+    g_err.clear();
+    if (!out) return fail(LB_E_ARG, "out is NULL");
+    *out = nullptr;
+    if (n_inst <= 0 || !p || !rho0 || !ux0 || !uy0 || !T0 || !d_workspace)
+        return fail(LB_E_ARG, "null argument or n_inst <= 0");
+    if (prec != LB_FP64 && prec != LB_FP32) return fail(LB_E_ARG, "bad precision");
+    if (reinterpret_cast<uintptr_t>(d_workspace) % ALIGN)
+        return fail(LB_E_ARG, "workspace must be %zu-byte aligned", ALIGN);
+    for (int k = 0; k < n_inst; ++k) {
+        lb_status s = validate_params(p[k], k);
+        if (s != LB_OK) return s;
+        if (!rho0[k] || !ux0[k] || !uy0[k] || !T0[k]) return fail(LB_E_ARG, "instance %d: null field", k);
+        const int64_t nc = (int64_t)p[k].nx * p[k].ny;
+        for (int64_t e = 0; e < nc; ++e) {
+            const double r = rho0[k][e], t = T0[k][e];
+            if (!(r > 0) || !(t > 0) || !(1.0 - p[k].vdw_b * r > 0) || !std::isfinite(ux0[k][e]) ||
+                !std::isfinite(uy0[k][e]) || !std::isfinite(r) || !std::isfinite(t))
+                return fail(LB_E_ARG, "instance %d cell %lld: need rho > 0, T > 0, 1 - vdw_b rho > 0 "
+                            "and finite u", k, (long long)e);
+        }
+    }
+    Layout lay = make_layout(n_inst, p, prec);
+    if (ws_bytes < lay.total)
+        return fail(LB_E_SIZE, "workspace of %zu bytes < %zu required", ws_bytes, lay.total);
+
+    lb_ctx* c = new (std::nothrow) lb_ctx();
+    if (!c) return fail(LB_E_NOMEM, "host allocation failed");
+    c->n = n_inst;
+    c->prec = prec;
+    c->p.assign(p, p + n_inst);
+    c->dvm = dvm ? *dvm : lb_dvm{1.0, 0.5, 2.0, 1.0, 2.5};
+    c->ws = reinterpret_cast<unsigned char*>(d_workspace);
+    c->ws_bytes = ws_bytes;
+    c->stream = reinterpret_cast<hipStream_t>(hip_stream);
+    c->lay = lay;
+    if (const char* g = std::getenv("LBFFT_NO_GRAPH")) c->use_graph = !(g[0] == '1');
+
+    if (!build_dvm(c->dvm, c->dvm64)) {
+        delete c;
+        return fail(LB_E_ARG, "the velocity set gives a singular moment matrix");
+    }
+    for (int i = 0; i < 16; ++i) {
+        c->dvm32.vx[i] = (float)c->dvm64.vx[i];
+        c->dvm32.vy[i] = (float)c->dvm64.vy[i];
+        c->dvm32.w[i] = (float)c->dvm64.w[i];
+        for (int j = 0; j < 16; ++j) c->dvm32.cinv[i][j] = (float)c->dvm64.cinv[i][j];
+    }
+    for (int i = 0; i < 16; ++i)
+        if (c->dvm64.vy[i] != 0.0) c->pops_h[c->npops++] = i;
+    build_jobs(*c);
+
+    // instance descriptors and size classes
+    const size_t w = word_bytes(prec);
+    c->hinst.resize(n_inst);
+    for (int k = 0; k < n_inst; ++k) {
+        InstDesc& I = c->hinst[k];
+        std::memset(&I, 0, sizeof(I));
+        I.nx = p[k].nx;
+        I.ny = p[k].ny;
+        I.ncell = (int64_t)p[k].nx * p[k].ny;
+        I.base = c->ws + lay.arena[k];
+        size_t t = lay.tables[k];
+        I.kx = c->ws + t;  t = align_up(t + w * I.nx);
+        I.ky = c->ws + t;  t = align_up(t + w * I.ny);
+        I.twx = c->ws + t; t = align_up(t + 2 * w * I.nx);
+        I.twy = c->ws + t;
+        I.red = c->dev<double>(lay.red);
+        I.dx = p[k].dx; I.dt = p[k].dt; I.tau = p[k].tau; I.K = p[k].K; I.H = p[k].H;
+        I.zeta = p[k].zeta; I.q = p[k].q; I.b = p[k].b_dof; I.a = p[k].vdw_a; I.bw = p[k].vdw_b;
+    }
+    std::vector<int> order;
+    for (int k = 0; k < n_inst; ++k) {
+        bool found = false;
+        for (auto& cl : c->classes)
+            if (cl.nx == p[k].nx && cl.ny == p[k].ny) found = true;
+        if (found) continue;
+        lb_ctx::Class cl{p[k].nx, p[k].ny, (int)order.size(), 0};
+        for (int j = 0; j < n_inst; ++j)
+            if (p[j].nx == cl.nx && p[j].ny == cl.ny) {
+                order.push_back(j);
+                ++cl.count;
+            }
+        c->classes.push_back(cl);
+    }
+    c->ilist_h = order;
+    for (int k = 0; k < n_inst; ++k) c->ilist_h.push_back(k);
+
+    lb_status st = LB_OK;
+    auto up = [&](size_t off, const void* src, size_t bytes) -> bool {
+        hipError_t e = hipMemcpyAsync(c->ws + off, src, bytes, hipMemcpyHostToDevice, c->stream);
+        if (e != hipSuccess) {
+            st = fail(LB_E_HIP, "upload failed: %s", hipGetErrorString(e));
+            return false;
+        }
+        return true;
+    };
+    bool ok = up(lay.insts, c->hinst.data(), sizeof(InstDesc) * n_inst) &&
+              up(lay.dvm64, &c->dvm64, sizeof(c->dvm64)) && up(lay.dvm32, &c->dvm32, sizeof(c->dvm32)) &&
+              up(lay.jobs, c->jobs.data(), sizeof(JobDesc) * c->jobs.size()) &&
+              up(lay.pops, c->pops_h, sizeof(int) * 16) &&
+              up(lay.ilist, c->ilist_h.data(), sizeof(int) * c->ilist_h.size());
+    if (ok) {
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) {
+            ok = false;
+            st = fail(LB_E_HIP, "sync failed: %s", hipGetErrorString(e));
+        }
+    }
+    // tables in float64, rounded to the working precision
+    for (int k = 0; ok && k < n_inst; ++k) {
+        hipError_t e = prec == LB_FP64 ? launch_tables<double>(c->d_insts(), k, p[k].nx, p[k].ny, c->stream)
+                                       : launch_tables<float>(c->d_insts(), k, p[k].nx, p[k].ny, c->stream);
+        if (e != hipSuccess) {
+            ok = false;
+            st = fail(LB_E_HIP, "table kernel: %s", hipGetErrorString(e));
+        }
+    }
+    // initial condition: stage (rho, ux, uy, T) as float64 in the F_B block, then f = f^eq
+    for (int k = 0; ok && k < n_inst; ++k) {
+        const InstDesc& I = c->hinst[k];
+        unsigned char* stage = reinterpret_cast<unsigned char*>(I.base) + (size_t)F_B * I.ncell * w;
+        const double* src[4] = {rho0[k], ux0[k], uy0[k], T0[k]};
+        for (int f = 0; ok && f < 4; ++f) {
+            hipError_t e = hipMemcpyAsync(stage + (size_t)f * I.ncell * 8, src[f], I.ncell * 8,
+                                          hipMemcpyHostToDevice, c->stream);
+            if (e != hipSuccess) {
+                ok = false;
+                st = fail(LB_E_HIP, "IC upload: %s", hipGetErrorString(e));
+            }
+        }
+        if (ok) {
+            hipError_t e = hipStreamSynchronize(c->stream);
+            if (e == hipSuccess) {
+                LaunchSet L = set_one(*c, k, c->stream);
+                e = prec == LB_FP64 ? launch_init<double>(L, c->dev<DvmConst<double>>(lay.dvm64))
+                                    : launch_init<float>(L, c->dev<DvmConst<double>>(lay.dvm64));
+            }
+            if (e != hipSuccess) {
+                ok = false;
+                st = fail(LB_E_HIP, "init kernel: %s", hipGetErrorString(e));
+            }
+        }
+    }
+    if (ok) {
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (e != hipSuccess) {
+            ok = false;
+            st = fail(LB_E_HIP, "init sync: %s", hipGetErrorString(e));
+        }
+    }
+    // capture one Runge-Kutta step into a graph (on a private stream of default priority)
+    if (ok && c->use_graph) {
+        hipStream_t cs;
+        hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        if (e == hipSuccess) {
+            e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+            if (e == hipSuccess) {
+                hipError_t e2 = enqueue_step(*c, cs);
+                e = hipStreamEndCapture(cs, &c->graph);
+                if (e2 != hipSuccess) e = e2;
+            }
+            if (e == hipSuccess) e = hipGraphInstantiate(&c->exec, c->graph, nullptr, nullptr, 0);
+            (void)hipStreamDestroy(cs);
+        }
+        if (e != hipSuccess) {
+            ok = false;
+            st = fail(LB_E_HIP, "graph capture: %s", hipGetErrorString(e));
+        }
+    }
+    if (!ok) {
+        lb_free(c);
+        return st;
+    }
+    *out = c;
+    return LB_OK;
+}
+
+lb_status lb_step(lb_ctx* c, int n_steps) {
+    if (!c) return fail(LB_E_ARG, "null context");
+    if (n_steps < 0) return fail(LB_E_ARG, "n_steps < 0");
+    for (int s = 0; s < n_steps; ++s) {
+        if (c->exec) {
+            LB_HIP(hipGraphLaunch(c->exec, c->stream));
+        } else {
+            LB_HIP(enqueue_step(*c, c->stream));
+        }
+    }
+    return LB_OK;
+}
+
+lb_status lb_sync(lb_ctx* c) {
+    if (!c) return fail(LB_E_ARG, "null context");
+    LB_HIP(hipStreamSynchronize(c->stream));
+    return LB_OK;
+}
+
+lb_status lb_moments(lb_ctx* c, int inst, double* rho, double* ux, double* uy, double* T) {
+    lb_status s = check_inst(c, inst);
+    if (s != LB_OK) return s;
+    LB_HIP(moments(*c, set_one(*c, inst, c->stream), F_A));
+    double* dst[4] = {rho, ux, uy, T};
+    for (int f = 0; f < 4; ++f)
+        if (dst[f] && (s = field_to_host(c, inst, RHO + f, dst[f])) != LB_OK) return s;
+    LB_HIP(hipStreamSynchronize(c->stream));
+    return LB_OK;
+}
+
+lb_status lb_conservation(lb_ctx* c, int inst, double out[4]) {
+    lb_status s = check_inst(c, inst);
+    if (s != LB_OK) return s;
+    if (!out) return fail(LB_E_ARG, "out is NULL");
+    const LaunchSet L = set_one(*c, inst, c->stream);
+    LB_HIP(moments(*c, L, F_A));
+    LB_HIP(macro(*c, L, 0, c->j_x1, c->n_x1));
+    LB_HIP(macro(*c, L, 1, c->j_y1, c->n_y1));
+    const int64_t nc = c->hinst[inst].ncell;
+    int nb = (int)((nc + 255) / 256);
+    if (nb > RED_BLOCKS) nb = RED_BLOCKS;
+    LB_HIP(c->prec == LB_FP64 ? launch_conserve<double>(c->d_insts(), inst, nb, c->stream)
+                              : launch_conserve<float>(c->d_insts(), inst, nb, c->stream));
+    std::vector<double> part(5 * nb);
+    LB_HIP(hipMemcpyAsync(part.data(), c->dev<double>(c->lay.red), sizeof(double) * 5 * nb,
+                          hipMemcpyDeviceToHost, c->stream));
+    LB_HIP(hipStreamSynchronize(c->stream));
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (int b = 0; b < nb; ++b)
+        for (int k = 0; k < 5; ++k) acc[k] += part[5 * b + k];
+    const double area = c->p[inst].dx * c->p[inst].dx;
+    for (int k = 0; k < 4; ++k) out[k] = acc[k] * area;
+    if (acc[4] != 0.0 || !std::isfinite(acc[0]) || !std::isfinite(acc[3]))
+        return fail(LB_E_NONFINITE, "instance %d holds %g non-finite cells", inst, acc[4]);
+    return LB_OK;
+}
+
+lb_status lb_get_f(lb_ctx* c, int inst, double* f) {
+    lb_status s = check_inst(c, inst);
+    if (s != LB_OK) return s;
+    if (!f) return fail(LB_E_ARG, "f is NULL");
+    return field_to_host(c, inst, F_A, f, 16);
+}
+
+lb_status lb_set_f(lb_ctx* c, int inst, const double* f) {
+    lb_status s = check_inst(c, inst);
+    if (s != LB_OK) return s;
+    if (!f) return fail(LB_E_ARG, "f is NULL");
+    return field_from_host(c, inst, F_A, f, 16);
+}
+
+lb_status lb_force_coefficients(lb_ctx* c, int inst, double* Bx, double* By, double* C) {
+    lb_status s = check_inst(c, inst);
+    if (s != LB_OK) return s;
+    LB_HIP(force_passes(*c, set_one(*c, inst, c->stream), F_A));
+    const int ct = c->p[inst].q != 0.0 ? CT : C0;
+    if (Bx && (s = field_to_host(c, inst, BX, Bx)) != LB_OK) return s;
+    if (By && (s = field_to_host(c, inst, BY, By)) != LB_OK) return s;
+    if (C && (s = field_to_host(c, inst, ct, C)) != LB_OK) return s;
+    return LB_OK;
+}
+
+lb_status lb_rhs(lb_ctx* c, int inst, double* R) {
+    lb_status s = check_inst(c, inst);
+    if (s != LB_OK) return s;
+    if (!R) return fail(LB_E_ARG, "R is NULL");
+    const LaunchSet L = set_one(*c, inst, c->stream);
+    LB_HIP(force_passes(*c, L, F_A));
+    StageArgs st{F_A, -1, F_B, 1.0, 0};
+    LB_HIP(pop_passes(*c, L, st));
+    return field_to_host(c, inst, F_B, R, 16);
+}
+
+lb_status lb_derivative(lb_ctx* c, int inst, int axis, int order, const double* g, double* out) {
+    lb_status s = check_inst(c, inst);
+    if (s != LB_OK) return s;
+    if (!g || !out) return fail(LB_E_ARG, "null field");
+    if ((axis != 0 && axis != 1) || (order != 1 && order != 2))
+        return fail(LB_E_ARG, "axis must be 0/1 and order 1/2");
+    if ((s = field_from_host(c, inst, SCR0, g)) != LB_OK) return s;
+    const int j = axis == 0 ? (order == 1 ? c->j_dx : c->j_dxx) : (order == 1 ? c->j_dy : c->j_dyy);
+    LB_HIP(macro(*c, set_one(*c, inst, c->stream), axis, j, 1));
+    return field_to_host(c, inst, SCR1, out);
+}
+
+void lb_free(lb_ctx* c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    if (c->exec) (void)hipGraphExecDestroy(c->exec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    delete c;
+}
+
+}  // extern "C"

@@ -1,0 +1,76 @@
+// Shared host/device data structures of the lbfft library: instance descriptors, field ids of
+// the per-instance arena and the job descriptors that drive the line-FFT passes.
+#pragma once
+#include <stdint.h>
+
+namespace lbfft {
+
+// Field ids inside one instance's arena.  Every field is nx*ny words of the working precision,
+// row-major [ny][nx].  Population blocks are 16 consecutive fields.
+enum FieldId : int {
+    F_A = 0,     // state f^n (and f^{n+1} after the step), 16 fields
+    F_B = 16,    // midpoint state f^{n+1/2}, 16 fields (also the rhs output of lb_rhs)
+    F_P = 32,    // per-population partial updates between the x and y passes, 16 fields
+    RHO = 48, UX, UY, TT,                        // moments (Sec. 2.1)
+    RX, RXX, TX, UXX, UYX, UXXX,                 // x-pass outputs: d_x rho, d_xx rho, d_x T,
+                                                 // d_x u_x, d_x u_y, d_xx u_x
+    RY, LAP, TY, UXY, UYY, GDX, GDY,             // y-pass outputs: d_y rho, lap rho, d_y T,
+                                                 // d_y u_x, d_y u_y, grad(div u)
+    SXX, SXY, SYY, C0, QX, QY,                   // stress S, C without C_q, q rho T grad T
+    DSXX, DSXY, DQX,                             // d_x of S_xx, S_xy, Q_x
+    BX, BY, CT,                                  // B and C + C_q of Eq. (2)
+    SCR0, SCR1,                                  // scratch for lb_derivative
+    NFIELDS
+};
+
+// Spectral multiplier kinds of a job term.
+enum MultKind : int8_t { M_NONE = 0, M_D = 1, M_DD = 2 };
+// Scale applied after the inverse transform (and the pre-addend).
+enum ScaleKind : int8_t { S_ONE = 0, S_INV_RHOT = 1, S_INV_RHOT2 = 2 };
+
+// One job of a macroscopic line pass:
+//   out[o] = post[o] + scale[o] * (pre[o] + IFFT( sum_k mult[o][k] * FFT(in[k]) ))
+// along the pass direction.  Unused slots hold -1 / M_NONE.  flag_q: the job only runs for
+// instances with q != 0.
+struct JobDesc {
+    int16_t in[2];
+    int16_t out[2];
+    int16_t pre[2];
+    int16_t post[2];
+    int8_t mult[2][2];
+    int8_t scale[2];
+    int8_t flag_q;
+    int8_t pad[3];
+};
+
+// Per-instance descriptor, stored in device memory.
+struct InstDesc {
+    int32_t nx, ny;
+    int64_t ncell;
+    void* base;            // field arena (NFIELDS * ncell words)
+    const void* kx;        // wavenumber k(m) of Eq. (3) along x, nx words
+    const void* ky;        // along y, ny words
+    const void* twx;       // forward twiddles exp(-2 pi i m / nx), nx complex words
+    const void* twy;       // ny complex words
+    double* red;           // reduction partials (float64)
+    double dx, dt, tau, K, H, zeta, q, b, a, bw;
+};
+
+// Context-wide constants (velocity set and the inverse moment matrix), stored in device
+// memory in both precisions.
+template <typename T>
+struct DvmConst {
+    T vx[16], vy[16], w[16];   // w = v^2 + eta^2
+    T cinv[16][16];            // inverse of the 16x16 moment matrix of the seven kinetic moments
+};
+
+// Stage description for the population passes.
+struct StageArgs {
+    int f_field;      // population block read (F_A or F_B)
+    int base_field;   // base population block of the Runge-Kutta axpy (-1: zero base)
+    int out_field;    // destination population block
+    double alpha;     // stage fraction: 1/2 (first stage) or 1 (second stage)
+    int use_dt;       // 1: the axpy coefficient is alpha * dt; 0: it is alpha (rhs diagnostic)
+};
+
+}  // namespace lbfft

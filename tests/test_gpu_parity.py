@@ -1,0 +1,206 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 CPU oracle on the same seeded
+inputs.  Bars: FP64 1e-12 relative per step on the state; FP32 1e-5 relative on rho and T after
+100 steps; derivatives and force coefficients at round-off of their own arithmetic."""
+import numpy as np
+import pytest
+
+from oracle import dvm as odvm
+from oracle import model, spectral
+from paper_1403_3746_amd import workloads as W
+from tests.gpu_util import field_errors, rel, say
+
+pytestmark = pytest.mark.gpu
+
+SIZES = (8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048)
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _sim(instances, precision="fp64"):
+    from paper_1403_3746_amd.lbfft import Sim
+    return Sim(instances, precision)
+
+
+def _moments(p):
+    return lambda f: model.moments(f, p)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+@pytest.mark.parametrize("n", SIZES)
+def test_derivative_every_line_length(torch_cuda, n, prec):
+    # x derivative on an n x 8 grid and y derivative on an 8 x n grid: every FFT instantiation
+    rng = np.random.default_rng(n)
+    dx = 0.7
+    tol = 2e-13 if prec == "fp64" else 3e-6
+    for nx, ny, axis in ((n, 8, 0), (8, n, 1)):
+        p = W.base_params(dx=dx)
+        sim = _sim([(p, W.slab(nx, ny, 0.5))], prec)
+        g = rng.normal(size=(ny, nx))
+        for order in (1, 2):
+            ref = spectral.dx_(g, dx) if axis == 0 else spectral.dy_(g, dx)
+            if order == 2:
+                ref = spectral.dx_(ref, dx) if axis == 0 else spectral.dy_(ref, dx)
+            out = sim.derivative(g, axis, order)
+            e = rel(out, ref)
+            say(f"derivative n={n} axis={axis} order={order} {prec}: rel err {e:.2e}")
+            assert e < tol * (1 + np.log2(n)) / 4
+        sim.close()
+
+
+@pytest.mark.parametrize("grid", [(2, 64), (1, 96), (2, 2048)])
+def test_quasi_1d_y_derivative_vanishes(torch_cuda, grid):
+    ny, nx = grid
+    p = W.base_params()
+    sim = _sim([(p, W.slab(nx, ny, 0.5))])
+    g = np.random.default_rng(1).normal(size=(ny, nx))
+    assert np.abs(sim.derivative(g, 1, 1)).max() == 0.0
+    ref = spectral.dx_(g, 1.0)
+    assert rel(sim.derivative(g, 0, 1), ref) < 1e-13
+    sim.close()
+
+
+CASES = [dict(), dict(q=-0.004, zeta=0.01, H=0.003), dict(b=3.0, q=0.02)]
+
+
+@pytest.mark.parametrize("kw", CASES)
+@pytest.mark.parametrize("grid", [(64, 64), (48, 96)])
+def test_force_coefficients_fp64(torch_cuda, kw, grid):
+    ny, nx = grid
+    p = W.base_params(**kw)
+    ic = W.smooth_random(nx, ny, 3, T0=0.5)
+    sim = _sim([(p, ic)])
+    f = sim.get_f()
+    rho, ux, uy, T = model.moments(f, p)
+    Bx, By, C, Cq = model.force_coefficients(rho, ux, uy, T, p)
+    gBx, gBy, gC = sim.force_coefficients()
+    errs = (rel(gBx, Bx), rel(gBy, By), rel(gC, C + Cq))
+    say(f"force {grid} {kw}: {errs}")
+    assert max(errs) < 1e-11
+    sim.close()
+
+
+@pytest.mark.parametrize("kw", CASES)
+def test_rhs_fp64(torch_cuda, kw):
+    ny, nx = 32, 48
+    p = W.base_params(**kw)
+    ic = W.smooth_random(nx, ny, 5, T0=0.5)
+    sim = _sim([(p, ic)])
+    f = sim.get_f()
+    rng = np.random.default_rng(7)
+    f = f * (1 + 0.01 * rng.uniform(-1, 1, f.shape))     # leave equilibrium
+    sim.set_f(f)
+    R = sim.rhs()
+    ref = model.rhs(f, p)
+    e = rel(R, ref)
+    say(f"rhs {kw}: {e:.2e}")
+    assert e < 1e-11
+    sim.close()
+
+
+def test_step_fp64_slab64_every_step(torch_cuda):
+    (p, ic), = W.config("slab64")[0]
+    sim = _sim([(p, ic)])
+    f_ref = model.init_equilibrium(*ic, p)
+    assert rel(sim.get_f(), f_ref) < 1e-14
+    worst = 0.0
+    for n in range(1, 101):
+        sim.step(1)
+        f_ref = model.rk2_step(f_ref, p)
+        errs = field_errors(sim.get_f(), f_ref, _moments(p))
+        worst = max(worst, max(errs.values()))
+        if n in (1, 10, 100):
+            say(f"slab64 fp64 step {n}: {errs}")
+        assert max(errs.values()) < 1e-12, (n, errs)
+    say(f"slab64 fp64 worst over 100 steps: {worst:.2e}")
+    sim.close()
+
+
+def test_step_fp64_nonsquare_with_all_terms(torch_cuda):
+    ny, nx = 96, 64
+    p = W.base_params(q=-0.004, zeta=0.01, H=0.003, dx=0.5)
+    ic = W.smooth_random(nx, ny, 11, T0=0.5)
+    sim = _sim([(p, ic)])
+    f_ref = model.init_equilibrium(*ic, p)
+    for n in range(1, 21):
+        sim.step(1)
+        f_ref = model.rk2_step(f_ref, p)
+        errs = field_errors(sim.get_f(), f_ref, _moments(p))
+        assert max(errs.values()) < 1e-12, (n, errs)
+    say(f"nonsquare fp64 step 20: {errs}")
+    sim.close()
+
+
+def test_step_fp32_quench_100(torch_cuda):
+    n = 128
+    p = W.base_params()
+    ic = W.quench(n, n, 0.9 * W.T_C, 2000)
+    sim = _sim([(p, ic)], "fp32")
+    f_ref = model.run(model.init_equilibrium(*ic, p), p, 100)
+    sim.step(100)
+    errs = field_errors(sim.get_f(), f_ref, _moments(p))
+    say(f"quench128 fp32 step 100: {errs}")
+    assert errs["rho"] < 1e-5 and errs["T"] < 1e-5
+    sim.close()
+
+
+def test_conservation_and_checkpoint(torch_cuda):
+    p = W.base_params(q=-0.004)
+    ic = W.smooth_random(64, 64, 13, T0=0.5)
+    sim = _sim([(p, ic)])
+    c0 = sim.conservation()
+    ref = model.conservation(model.init_equilibrium(*ic, p), p)
+    say(f"conservation gpu {c0} oracle {ref}")
+    assert abs(c0[0] - ref[0]) < 1e-12 * abs(ref[0])
+    assert abs(c0[3] - ref[3]) < 1e-11 * abs(ref[3])
+    sim.step(5)
+    f5 = sim.get_f()
+    sim.step(5)
+    f10 = sim.get_f()
+    c1 = sim.conservation()
+    assert abs(c1[0] - c0[0]) < 1e-12 * abs(c0[0])
+    assert abs(c1[1] - c0[1]) < 1e-12 * abs(c0[0]) and abs(c1[2] - c0[2]) < 1e-12 * abs(c0[0])
+    sim.set_f(f5)
+    sim.step(5)
+    assert np.array_equal(sim.get_f(), f10)
+    sim.close()
+
+
+def test_nonfinite_state_is_reported(torch_cuda):
+    from paper_1403_3746_amd import lbfft
+    p = W.base_params()
+    sim = _sim([(p, W.slab(32, 32, 0.5))])
+    f = sim.get_f()
+    f[3, 5, 7] = np.nan
+    sim.set_f(f)
+    with pytest.raises(lbfft.LBError) as e:
+        sim.conservation()
+    assert e.value.status == lbfft.LB_E_NONFINITE
+    sim.close()
+
+
+def test_ragged_batch_matches_solo_and_oracle(torch_cuda):
+    # three sizes, four instances, one context: each instance equals its solo run bitwise and the
+    # oracle within the FP64 bar after 10 steps.
+    insts = [(W.base_params(), W.slab(64, 64, 0.52)),
+             (W.base_params(), W.quench(96, 96, 0.53, 5)),
+             (W.base_params(q=-0.004), W.quench(64, 64, 0.55, 6)),
+             (W.base_params(), W.slab(128, 32, 0.5))]
+    sim = _sim(insts)
+    sim.step(10)
+    for k, (p, ic) in enumerate(insts):
+        solo = _sim([(p, ic)])
+        solo.step(10)
+        fb, fs = sim.get_f(k), solo.get_f()
+        assert np.array_equal(fb, fs), k
+        f_ref = model.run(model.init_equilibrium(*ic, p), p, 10)
+        errs = field_errors(fb, f_ref, _moments(p))
+        say(f"batch inst {k} {ic[0].shape}: {errs}")
+        assert max(errs.values()) < 1e-12
+        solo.close()
+    sim.close()
