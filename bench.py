@@ -1,0 +1,188 @@
+"""Benchmark of the D2V16 windowed-FFT thermal LB step on one MI355X.
+
+Prints ONE JSON line.  The headline workload is the 512x512 thermal quench (rho = rho_c (1 +
+0.001 U(-1,1)), u = 0, T = 0.9 T_c, seed 2000) in FP64; the FP32 form of the same grid and the
+FP32 batch of 256 independent 128x128 quenches (per-instance T in [0.85, 0.98] T_c) are reported
+as variants.  A "step" is one full RK2 step of every instance (two evaluations of R(f): moments,
+macroscopic spectral derivatives, forcing, population x and y passes).  Inputs are resident in
+HBM before timing starts; the timed region replays the captured step graph.
+
+roofline: algorithmic HBM words per cell of each pass (listed in ALG_WORDS) times cells, over the
+pass's mean launch duration from HIP events recorded on the library's stream during a second run
+of steps (lb_step_timed); the dominant pass (largest time per step) is reported.
+cpu_baseline: the FP64 CPU oracle stepping the same 512x512 initial condition for a bounded number
+of steps on the host cores.
+"""
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "MLUPS (cells×RK2 steps/s) FP32-batched vs FP64-plain; % of HBM roofline"
+HBM_PEAK_GBS = 8000.0
+
+# Algorithmic words per cell of one launch of each pass (q = 0), averaged over the two RK
+# stages (only pop_x differs: 39 words in stage 1, 55 in stage 2 where the base f^n is read).
+ALG_WORDS = {
+    "moments": 20,     # read 16 f, write rho, ux, uy, T
+    "macro_x1": 10,    # read rho, T, ux, uy; write 6 x-derivatives
+    "macro_y1": 15,    # read 8 fields; write 7 (d_y terms, lap rho, grad div u)
+    "stress": 17,      # read 13; write S_xx, S_xy, S_yy, C
+    "macro_x2": 4,     # read S_xx, S_xy; write their x-derivatives
+    "macro_y2": 8,     # read S_xy, S_yy, 2 x-derivatives, rho, T; write B_x, B_y
+    "pop_x": 47,       # read 16 f + 7 coefficients (+16 base in stage 2); write 16
+    "pop_y": 36,       # read 12 f + 12 partials; write 12
+}
+WORDS_PER_STEP = 2 * sum(ALG_WORDS.values())   # 314
+
+
+def kernel_source_hash():
+    h = hashlib.sha256()
+    for f in ("lb_kernels.h", "lb_fft.h", "lb_lines.inc"):
+        h.update(open(os.path.join(ROOT, "paper_1403_3746_amd", "csrc", f), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(workload, pass_name):
+    """HBM traffic per launch from committed rocprofv3 counter runs, if they were taken on the
+    current kernel sources (else None)."""
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    try:
+        d = json.load(open(path))
+        ent = d.get(workload, {}).get(pass_name)
+        if ent and ent.get("kernel_source_hash") == kernel_source_hash():
+            return ent["bytes_per_launch"]
+    except Exception:
+        return None
+    return None
+
+
+def run_gpu(instances, precision, steps, warmup, timed_steps):
+    import torch
+    from paper_1403_3746_amd.lbfft import Sim
+
+    sim = Sim(instances, precision)
+    cells = sum(ic[0].size for _, ic in instances)
+    sim.step(warmup)
+    sim.sync()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.step(steps)
+    sim.sync()
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    passes = sim.step_timed(timed_steps)
+    sim.sync()
+    c = sim.conservation(0)
+    sim.close()
+    if not np.all(np.isfinite(c)):
+        raise RuntimeError("non-finite state after the benchmark")
+    dt = t1 - t0
+    return dict(mlups=cells * steps / dt / 1e6, ms_per_step=1e3 * dt / steps, cells=cells,
+                passes=passes)
+
+
+def roofline(res, word_bytes, workload):
+    cells = res["cells"]
+    per_pass = {}
+    for name, ms in res["passes"].items():
+        if ms <= 0:
+            continue
+        alg = ALG_WORDS[name] * word_bytes * cells
+        per_pass[name] = dict(ms=ms, alg_bytes=alg, gbs=alg / (ms * 1e-3) / 1e9)
+    dom = max(per_pass, key=lambda k: per_pass[k]["ms"])
+    d = per_pass[dom]
+    traffic = load_traffic(workload, dom)
+    return dict(bound="hbm", kernel=dom, achieved=round(d["gbs"], 1), peak=HBM_PEAK_GBS,
+                unit="GB/s", frac=round(d["gbs"] / HBM_PEAK_GBS, 4), traffic=traffic,
+                alg_bytes_per_launch=d["alg_bytes"], mean_launch_ms=round(d["ms"], 5),
+                passes={k: dict(ms=round(v["ms"], 5), gbs=round(v["gbs"], 1)) for k, v in per_pass.items()},
+                step_frac=round(res["mlups"] * 1e6 * WORDS_PER_STEP * word_bytes / 1e9 / HBM_PEAK_GBS, 4))
+
+
+def cpu_baseline(instances, budget_s=15.0):
+    from oracle import model, spectral
+
+    workers = os.cpu_count() or 1
+    spectral.set_workers(workers)
+    p, ic = instances[0]
+    f = model.init_equilibrium(*ic, p)
+    t0 = time.perf_counter()
+    f = model.rk2_step(f, p)
+    t1 = time.perf_counter() - t0
+    n = int(max(1, min(20, budget_s / max(t1, 1e-3))))
+    t0 = time.perf_counter()
+    for _ in range(n):
+        f = model.rk2_step(f, p)
+    dt = time.perf_counter() - t0
+    cells = ic[0].size
+    spectral.set_workers(1)
+    return dict(value=round(cells * n / dt / 1e6, 4), unit="MLUPS", cores=workers, kind="oracle",
+                sample=f"FP64 oracle, {ic[0].shape[1]}x{ic[0].shape[0]} quench, {n} RK2 steps after 1 "
+                       f"warm-up step, scipy.fft workers={workers}")
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=2000)
+    ap.add_argument("--warmup", type=int, default=100)
+    ap.add_argument("--timed-steps", type=int, default=50)
+    ap.add_argument("--no-variants", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding is a "
+                                   "design note, not built"}))
+        sys.exit(2)
+
+    from paper_1403_3746_amd import workloads as W
+
+    insts, _ = W.config("quench512")
+    main_res = run_gpu(insts, "fp64", args.steps, args.warmup, args.timed_steps)
+    out = {
+        "metric": METRIC,
+        "value": round(main_res["mlups"], 2),
+        "unit": "MLUPS",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(main_res["ms_per_step"], 5),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "quench512: 512x512 periodic thermal quench, FP64, one instance",
+                   "grid": [512, 512], "instances": 1, "precision": "fp64",
+                   "params": "dx=1 dt=1e-3 tau=1e-2 K=1e-2 a=9/49 b_w=2/21 T=0.9T_c b=2 H=zeta=q=0"},
+        "roofline": roofline(main_res, 8, "quench512_fp64"),
+    }
+    if not args.no_variants:
+        var = {}
+        r32 = run_gpu(insts, "fp32", args.steps, args.warmup, args.timed_steps)
+        var["quench512_fp32"] = dict(mlups=round(r32["mlups"], 2), ms_per_step=round(r32["ms_per_step"], 5),
+                                     roofline=roofline(r32, 4, "quench512_fp32"))
+        binsts, _ = W.config("batch128x256")
+        bsteps = max(1, args.steps // 4)
+        rb = run_gpu(binsts, "fp32", bsteps, max(1, args.warmup // 4), max(1, args.timed_steps // 4))
+        var["batch128x256_fp32"] = dict(mlups=round(rb["mlups"], 2), ms_per_step=round(rb["ms_per_step"], 5),
+                                        steps=bsteps, roofline=roofline(rb, 4, "batch128x256_fp32"))
+        var["fp32_batched_over_fp64_plain"] = round(rb["mlups"] / main_res["mlups"], 3)
+        out["variants"] = var
+    if not args.no_cpu:
+        out["cpu_baseline"] = cpu_baseline(insts)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -158,6 +158,13 @@ constexpr int plan_ns(const Plan& p, int s) {
     return ns;
 }
 
+// LDS index of line element i: one padding word after every 8 elements, so the stride-r writes of
+// a Stockham pass (r = 2..8 complex words apart in consecutive lanes) spread over the banks.
+constexpr int LDS_PAD_SHIFT = 3;
+__host__ __device__ constexpr int lds_idx(int i) { return i + (i >> LDS_PAD_SHIFT); }
+// LDS words reserved per line of length N.
+__host__ __device__ constexpr int lds_line(int N) { return N + (N >> LDS_PAD_SHIFT) + 1; }
+
 template <typename T>
 __device__ __forceinline__ cpx<T> ld_tw(const cpx<T>* __restrict__ tw, int idx) {
     return tw[idx];
@@ -180,7 +187,7 @@ __device__ __forceinline__ void stockham_pass(cpx<T> (&v)[R], cpx<T>* lds, int t
         for (int b = 0; b < NB; ++b) {
             const int j = t + b * TPL;
 #pragma unroll
-            for (int q = 0; q < r; ++q) a[b * r + q] = lds[j + q * (N / r)];
+            for (int q = 0; q < r; ++q) a[b * r + q] = lds[lds_idx(j + q * (N / r))];
         }
         __syncthreads();
     }
@@ -203,7 +210,7 @@ __device__ __forceinline__ void stockham_pass(cpx<T> (&v)[R], cpx<T>* lds, int t
         } else {
             const int base = (j / Ns) * Ns * r + k;
 #pragma unroll
-            for (int q = 0; q < r; ++q) lds[base + q * Ns] = a[b * r + q];
+            for (int q = 0; q < r; ++q) lds[lds_idx(base + q * Ns)] = a[b * r + q];
         }
     }
     if constexpr (!TO_REG) __syncthreads();
@@ -240,13 +247,13 @@ struct LineFFT {
             constexpr bool last_reg = (P.r[P.np - 1] == R);
             if constexpr (!first_reg) {
 #pragma unroll
-                for (int m = 0; m < R; ++m) lds[t + m * TPL] = v[m];
+                for (int m = 0; m < R; ++m) lds[lds_idx(t + m * TPL)] = v[m];
                 __syncthreads();
             }
             passes<0>(v, lds, t, tw);
             if constexpr (!last_reg) {
 #pragma unroll
-                for (int m = 0; m < R; ++m) v[m] = lds[t + m * TPL];
+                for (int m = 0; m < R; ++m) v[m] = lds[lds_idx(t + m * TPL)];
             }
             // the next transform may write LDS that slower threads are still reading
             if constexpr (!(P.np == 1 && first_reg && last_reg)) __syncthreads();

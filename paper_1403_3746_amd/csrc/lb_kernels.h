@@ -18,60 +18,73 @@
 #include "lb_fft.h"
 #include "lb_types.h"
 
+#ifndef LB_EPI_GROUP
+#define LB_EPI_GROUP 4   // epilogue positions whose field loads may be hoisted together
+#endif
+
 namespace lbfft {
 
 // ---------------------------------------------------------------------------------------
-// Launch geometry of the line passes.
+// Launch geometry of the line passes.  Small tiles keep many blocks in flight for a single grid;
+// y tiles span LPW column pairs (2*LPW*sizeof(T) bytes of each row), and neighbouring tiles run
+// on the same XCD (see decode_block) so partially used cache lines are reused from L2.
 template <typename T, int N, int DIR>
 struct LineCfg {
     static constexpr int R = default_R(N);
     static constexpr int TPL = N / R;
     static constexpr int CB = 2 * (int)sizeof(T);  // bytes of one complex word
-    static constexpr int lpw_x() {
-        int l = 256 / TPL;
-        return l < 1 ? 1 : l;
-    }
-    static constexpr int pow2_floor(int x) {
-        int p = 1;
-        while (p * 2 <= x) p *= 2;
-        return p;
-    }
+    static constexpr int at_least(int l, int lo) { return l < lo ? lo : l; }
+    // x: one line per block unless lines are short (then fill one wave)
+    static constexpr int lpw_x() { return at_least(64 / TPL, 1); }
+    // y: 32-byte row segments, at least one wave per block
     static constexpr int lpw_y() {
-        int want = 128 / CB;                    // 128-byte row segments
-        int small = 256 / TPL;                  // keep >= 256 threads for short lines
-        if (small > want) want = small;
-        int by_thr = 1024 / TPL;
-        int by_lds = (128 * 1024) / (N * CB);
-        int l = want;
-        if (l > by_thr) l = by_thr;
-        if (l > by_lds) l = by_lds;
-        l = pow2_floor(l < 1 ? 1 : l);
-        return l;
+        int l = at_least(at_least(32 / CB, 64 / TPL), 1);
+        return (l * TPL > 512) ? at_least(512 / TPL, 1) : l;   // cap the block at 512 threads
     }
     static constexpr int LPW = DIR == 0 ? lpw_x() : lpw_y();
     static constexpr int WG = LPW * TPL;
-    static constexpr int LDS = LPW * N;   // complex words
+    static constexpr int LDS = LPW * lds_line(N);   // complex words
 };
 
-// Decode the flat block index into (instance, tile, job).  Blocks of the same (instance, tile)
-// group land on the same XCD (workgroups are dealt to the 8 XCDs round-robin) so that their
-// shared coefficient reads hit one L2.
+// Decode the flat block index into (instance, tile, job).  Workgroups are dealt to the 8 XCDs
+// round-robin (block b runs on XCD b mod 8); each XCD gets a contiguous range of (instance, tile)
+// groups and runs all jobs of a group back to back, so the coefficient fields a group's jobs share
+// and the cache lines that neighbouring tiles split stay in that XCD's L2.
 struct BlockWork {
     int inst_local, tile, job;
     bool valid;
 };
 
+__host__ __device__ constexpr int groups_per_xcd(int ngroups) { return (ngroups + 7) / 8; }
+
 __device__ __forceinline__ BlockWork decode_block(int ngroups, int ntiles, int njobs) {
     const int b = blockIdx.x;
     const int xcd = b & 7;
     const int slot = b >> 3;
-    const int group = (slot / njobs) * 8 + xcd;
+    const int gpx = groups_per_xcd(ngroups);
+    const int g_local = slot / njobs;
+    const int group = xcd * gpx + g_local;
     BlockWork w;
     w.job = slot % njobs;
-    w.valid = group < ngroups;
+    w.valid = g_local < gpx && group < ngroups;
     w.inst_local = group / ntiles;
     w.tile = group % ntiles;
     return w;
+}
+
+// Spectral multiplier kind mk applied to coefficient x of wavenumber k, including the 1/N of the
+// inverse transform:  M_D -> i (k/N) x,  M_DD -> -(k^2/N) x,  M_NONE -> 0.
+template <typename T>
+__device__ __forceinline__ cpx<T> spectral_mult(int mk, T k, T invN, cpx<T> x) {
+    if (mk == M_D) {
+        const T a = k * invN;
+        return {-a * x.im, a * x.re};
+    }
+    if (mk == M_DD) {
+        const T a = -k * k * invN;
+        return {a * x.re, a * x.im};
+    }
+    return {T(0), T(0)};
 }
 
 template <typename T>
@@ -134,53 +147,47 @@ macro_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
     const int nx = I.nx, ny = I.ny;
     const int nlines = DIR == 0 ? (ny + 1) / 2 : nx / 2;
     const bool active = line < nlines;
-    cpx<T>* lds = lds_all + l * N;
+    cpx<T>* lds = lds_all + l * lds_line(N);
     T* fld = reinterpret_cast<T*>(I.base);
     const int64_t nc = I.ncell;
     const T* __restrict__ kap = reinterpret_cast<const T*>(DIR == 0 ? I.kx : I.ky);
     const cpx<T>* __restrict__ tw = reinterpret_cast<const cpx<T>*>(DIR == 0 ? I.twx : I.twy);
 
-    cpx<T> X0[R], X1[R];
-    load_line<T, DIR, R, TPL>(fld + J.in[0] * nc, X0, line, t, nx, ny, active);
-    LineFFT<T, N, R, false>::run(X0, lds, t, tw);
-    const bool two = J.in[1] >= 0;
-    if (two) {
-        load_line<T, DIR, R, TPL>(fld + J.in[1] * nc, X1, line, t, nx, ny, active);
-        LineFFT<T, N, R, false>::run(X1, lds, t, tw);
-    }
+    // spectrum of the first input
+    cpx<T> X[R], Y[R];
+    load_line<T, DIR, R, TPL>(fld + J.in[0] * nc, X, line, t, nx, ny, active);
+    LineFFT<T, N, R, false>::run(X, lds, t, tw);
     const T invN = T(1.0 / N);
-#pragma unroll
+    const bool two = J.in[1] >= 0;   // two inputs: a single output from the summed spectra
+#pragma unroll 1
     for (int o = 0; o < 2; ++o) {
-        if (J.out[o] < 0) continue;
-        cpx<T> Y[R];
+        // select the job slots without runtime indexing (which would go through scratch)
+        const int outf = o == 0 ? J.out[0] : J.out[1];
+        if (outf < 0) continue;
+        const int mk0 = o == 0 ? J.mult[0][0] : J.mult[1][0];
+        const int mk1 = o == 0 ? J.mult[0][1] : J.mult[1][1];
+        const int pre = o == 0 ? J.pre[0] : J.pre[1];
+        const int post = o == 0 ? J.post[0] : J.post[1];
+        const int sc = o == 0 ? J.scale[0] : J.scale[1];
 #pragma unroll
-        for (int m = 0; m < R; ++m) {
-            const int k = t + m * TPL;
-            const T kk = kap[k];
-            cpx<T> y = {T(0), T(0)};
+        for (int m = 0; m < R; ++m) Y[m] = spectral_mult<T>(mk0, kap[t + m * TPL], invN, X[m]);
+        if (two) {
+            // X is no longer needed: transform the second input in its place
+            load_line<T, DIR, R, TPL>(fld + J.in[1] * nc, X, line, t, nx, ny, active);
+            LineFFT<T, N, R, false>::run(X, lds, t, tw);
 #pragma unroll
-            for (int s = 0; s < 2; ++s) {
-                const int mk = J.mult[o][s];
-                if (s == 1 && !two) continue;
-                const cpx<T> x = s == 0 ? X0[m] : X1[m];
-                if (mk == M_D) {          // i k / N
-                    const T a = kk * invN;
-                    y.re -= a * x.im;
-                    y.im += a * x.re;
-                } else if (mk == M_DD) {  // -k^2 / N
-                    const T a = -kk * kk * invN;
-                    y.re += a * x.re;
-                    y.im += a * x.im;
-                }
+            for (int m = 0; m < R; ++m) {
+                const cpx<T> z = spectral_mult<T>(mk1, kap[t + m * TPL], invN, X[m]);
+                Y[m] = cadd(Y[m], z);
             }
-            Y[m] = y;
         }
         LineFFT<T, N, R, true>::run(Y, lds, t, tw);
         if (!active) continue;
-        const int pre = J.pre[o], post = J.post[o], sc = J.scale[o];
-        T* __restrict__ out = fld + J.out[o] * nc;
+        T* __restrict__ out = fld + outf * nc;
 #pragma unroll
         for (int m = 0; m < R; ++m) {
+            // compiler fence: bounds how many epilogue loads are hoisted (register pressure)
+            if (m % LB_EPI_GROUP == 0) asm volatile("" ::: "memory");
             const int p = t + m * TPL;
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
@@ -196,6 +203,7 @@ macro_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
                 out[e] = val;
             }
         }
+        if (two) break;
     }
 }
 
@@ -239,7 +247,7 @@ pop_x_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
     const int line = w.tile * C::LPW + l;
     const int nx = I.nx, ny = I.ny;
     const bool active = line < (ny + 1) / 2;
-    cpx<T>* lds = lds_all + l * N;
+    cpx<T>* lds = lds_all + l * lds_line(N);
     T* fld = reinterpret_cast<T*>(I.base);
     const int64_t nc = I.ncell;
     const T vx = D.vx[i], vy = D.vy[i];
@@ -273,6 +281,7 @@ pop_x_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
     const T* basep = st.base_field >= 0 ? fld + (st.base_field + i) * nc : nullptr;
 #pragma unroll
     for (int m = 0; m < R; ++m) {
+        if (m % LB_EPI_GROUP == 0) asm volatile("" ::: "memory");
         const int p = t + m * TPL;
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
@@ -312,7 +321,7 @@ pop_y_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
     const int line = w.tile * LPW + l;
     const int nx = I.nx, ny = I.ny;
     const bool active = line < nx / 2;
-    cpx<T>* lds = lds_all + l * N;
+    cpx<T>* lds = lds_all + l * lds_line(N);
     T* fld = reinterpret_cast<T*>(I.base);
     const int64_t nc = I.ncell;
     const T vy = dvm->vy[i];

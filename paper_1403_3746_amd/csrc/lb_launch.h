@@ -1,5 +1,6 @@
 // Internal launch interface between the host runtime and the kernel units.
 #pragma once
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "lb_types.h"
@@ -14,7 +15,19 @@ struct LaunchSet {
     int ninst;
     int nx, ny;
     hipStream_t stream;
+    // when set, the launch timestamps its own start and end into these events
+    hipEvent_t ev_start = nullptr, ev_stop = nullptr;
 };
+
+// Launch through hipExtLaunchKernelGGL when the set carries timing events.
+#define LB_LAUNCH(L, kernel, grid, block, ...)                                                  \
+    do {                                                                                        \
+        if ((L).ev_start)                                                                       \
+            hipExtLaunchKernelGGL(kernel, grid, block, 0, (L).stream, (L).ev_start, (L).ev_stop, \
+                                  0, __VA_ARGS__);                                              \
+        else                                                                                    \
+            hipLaunchKernelGGL(kernel, grid, block, 0, (L).stream, __VA_ARGS__);                \
+    } while (0)
 
 // Line passes (lb_lines_<dir>_<prec>.hip).
 hipError_t macro_x_f64(const LaunchSet& L, const JobDesc* jobs, int njobs);

@@ -48,16 +48,15 @@ tables_kernel(const InstDesc* __restrict__ insts, int inst) {
 template <typename T>
 hipError_t launch_moments(const LaunchSet& L, const DvmConst<T>* dvm, int f_field) {
     const int64_t nc = (int64_t)L.nx * L.ny;
-    hipLaunchKernelGGL((moments_kernel<T>), cell_grid(nc, L.ninst), dim3(256), 0, L.stream,
-                       L.insts, L.ilist, dvm, f_field);
+    LB_LAUNCH(L, (moments_kernel<T>), cell_grid(nc, L.ninst), dim3(256), L.insts, L.ilist, dvm,
+              f_field);
     return hipGetLastError();
 }
 
 template <typename T>
 hipError_t launch_stress(const LaunchSet& L) {
     const int64_t nc = (int64_t)L.nx * L.ny;
-    hipLaunchKernelGGL((stress_kernel<T>), cell_grid(nc, L.ninst), dim3(256), 0, L.stream,
-                       L.insts, L.ilist);
+    LB_LAUNCH(L, (stress_kernel<T>), cell_grid(nc, L.ninst), dim3(256), L.insts, L.ilist);
     return hipGetLastError();
 }
 

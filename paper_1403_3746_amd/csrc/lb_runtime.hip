@@ -301,49 +301,77 @@ hipError_t stress(const lb_ctx& c, const LaunchSet& L) {
     return c.prec == LB_FP64 ? launch_stress<double>(L) : launch_stress<float>(L);
 }
 
+// Optional timing hook: supplies a start/stop event pair for every launch of a pass.
+struct PassHook {
+    virtual bool events(int pass, hipEvent_t* start, hipEvent_t* stop) = 0;
+    virtual ~PassHook() = default;
+};
+
+hipError_t pop_x(const lb_ctx& c, const LaunchSet& L, StageArgs st) {
+    const int* pops = c.dev<int>(c.lay.pops);
+    if (c.prec == LB_FP64) return pop_x_f64(L, c.dev<DvmConst<double>>(c.lay.dvm64), pops, c.npops, st);
+    return pop_x_f32(L, c.dev<DvmConst<float>>(c.lay.dvm32), pops, c.npops, st);
+}
+
+hipError_t pop_y(const lb_ctx& c, const LaunchSet& L, StageArgs st) {
+    const int* pops = c.dev<int>(c.lay.pops);
+    if (c.prec == LB_FP64) return pop_y_f64(L, c.dev<DvmConst<double>>(c.lay.dvm64), pops, c.npops, st);
+    return pop_y_f32(L, c.dev<DvmConst<float>>(c.lay.dvm32), pops, c.npops, st);
+}
+
+// Launch pass `kind` of one stage for the instances of L.
+hipError_t run_pass(const lb_ctx& c, const LaunchSet& L, int kind, StageArgs st) {
+    switch (kind) {
+        case LB_PASS_MOMENTS: return moments(c, L, st.f_field);
+        case LB_PASS_MACRO_X1: return macro(c, L, 0, c.j_x1, c.n_x1);
+        case LB_PASS_MACRO_Y1: return macro(c, L, 1, c.j_y1, c.n_y1);
+        case LB_PASS_STRESS: return stress(c, L);
+        case LB_PASS_MACRO_X2: return macro(c, L, 0, c.j_x2, c.n_x2);
+        case LB_PASS_MACRO_Y2: return macro(c, L, 1, c.j_y2, c.n_y2);
+        case LB_PASS_POP_X: return pop_x(c, L, st);
+        case LB_PASS_POP_Y: return pop_y(c, L, st);
+    }
+    return hipErrorInvalidValue;
+}
+
 // Moments and the force coefficients B, C (+ C_q) of the population block f_field.
 hipError_t force_passes(const lb_ctx& c, const LaunchSet& L, int f_field) {
-    hipError_t e;
-    if ((e = moments(c, L, f_field)) != hipSuccess) return e;
-    if ((e = macro(c, L, 0, c.j_x1, c.n_x1)) != hipSuccess) return e;
-    if ((e = macro(c, L, 1, c.j_y1, c.n_y1)) != hipSuccess) return e;
-    if ((e = stress(c, L)) != hipSuccess) return e;
-    if ((e = macro(c, L, 0, c.j_x2, c.n_x2)) != hipSuccess) return e;
-    return macro(c, L, 1, c.j_y2, c.n_y2);
+    StageArgs st{f_field, -1, -1, 0.0, 0};
+    for (int k = LB_PASS_MOMENTS; k <= LB_PASS_MACRO_Y2; ++k) {
+        hipError_t e = run_pass(c, L, k, st);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
 }
 
 hipError_t pop_passes(const lb_ctx& c, const LaunchSet& L, StageArgs st) {
-    hipError_t e;
-    const int* pops = c.dev<int>(c.lay.pops);
-    if (c.prec == LB_FP64) {
-        const auto* d = c.dev<DvmConst<double>>(c.lay.dvm64);
-        if ((e = pop_x_f64(L, d, pops, c.npops, st)) != hipSuccess) return e;
-        return pop_y_f64(L, d, pops, c.npops, st);
-    }
-    const auto* d = c.dev<DvmConst<float>>(c.lay.dvm32);
-    if ((e = pop_x_f32(L, d, pops, c.npops, st)) != hipSuccess) return e;
-    return pop_y_f32(L, d, pops, c.npops, st);
+    hipError_t e = pop_x(c, L, st);
+    if (e != hipSuccess) return e;
+    return pop_y(c, L, st);
 }
 
-// One Runge-Kutta stage of every instance on stream s.
-hipError_t enqueue_stage(const lb_ctx& c, hipStream_t s, StageArgs st) {
-    hipError_t e;
-    for (const auto& k : c.classes) {
-        LaunchSet L = set_of(c, k);
-        L.stream = s;
-        if ((e = force_passes(c, L, st.f_field)) != hipSuccess) return e;
-        if ((e = pop_passes(c, L, st)) != hipSuccess) return e;
+// One Runge-Kutta stage of every instance on stream s: each pass kind is launched for every
+// size class before the next pass kind.
+hipError_t enqueue_stage(const lb_ctx& c, hipStream_t s, StageArgs st, PassHook* hook = nullptr) {
+    for (int k = 0; k < LB_NPASS; ++k) {
+        for (const auto& cl : c.classes) {
+            LaunchSet L = set_of(c, cl);
+            L.stream = s;
+            if (hook && !hook->events(k, &L.ev_start, &L.ev_stop)) return hipErrorInvalidValue;
+            hipError_t e = run_pass(c, L, k, st);
+            if (e != hipSuccess) return e;
+        }
     }
     return hipSuccess;
 }
 
 // f^{n+1/2} = f^n + dt/2 R(f^n) into F_B;  f^{n+1} = f^n + dt R(f^{n+1/2}) into F_A.
-hipError_t enqueue_step(const lb_ctx& c, hipStream_t s) {
+hipError_t enqueue_step(const lb_ctx& c, hipStream_t s, PassHook* hook = nullptr) {
     StageArgs s1{F_A, F_A, F_B, 0.5, 1};
     StageArgs s2{F_B, F_A, F_A, 1.0, 1};
-    hipError_t e = enqueue_stage(c, s, s1);
+    hipError_t e = enqueue_stage(c, s, s1, hook);
     if (e != hipSuccess) return e;
-    return enqueue_stage(c, s, s2);
+    return enqueue_stage(c, s, s2, hook);
 }
 
 lb_status check_inst(const lb_ctx* c, int inst) {
@@ -603,6 +631,55 @@ lb_status lb_step(lb_ctx* c, int n_steps) {
         }
     }
     return LB_OK;
+}
+
+namespace {
+// One start/stop event pair per launch, tagged with its pass kind.
+struct EventHook : PassHook {
+    std::vector<hipEvent_t> ev;
+    std::vector<int> kind;
+    size_t next = 0;
+    bool events(int pass, hipEvent_t* start, hipEvent_t* stop) override {
+        if (2 * next + 1 >= ev.size()) return false;
+        kind[next] = pass;
+        *start = ev[2 * next];
+        *stop = ev[2 * next + 1];
+        ++next;
+        return true;
+    }
+};
+}  // namespace
+
+lb_status lb_step_timed(lb_ctx* c, int n_steps, double ms[LB_NPASS]) {
+    if (!c) return fail(LB_E_ARG, "null context");
+    if (n_steps <= 0 || !ms) return fail(LB_E_ARG, "need n_steps > 0 and an output array");
+    EventHook h;
+    const size_t nlaunch = (size_t)n_steps * 2 * LB_NPASS * c->classes.size();
+    h.ev.resize(2 * nlaunch, nullptr);
+    h.kind.resize(nlaunch, -1);
+    lb_status st = LB_OK;
+    for (size_t k = 0; k < h.ev.size() && st == LB_OK; ++k)
+        if (hipEventCreate(&h.ev[k]) != hipSuccess) st = fail(LB_E_HIP, "hipEventCreate failed");
+    for (int s = 0; s < n_steps && st == LB_OK; ++s) {
+        hipError_t e = enqueue_step(*c, c->stream, &h);
+        if (e != hipSuccess) st = fail(LB_E_HIP, "step launch: %s", hipGetErrorString(e));
+    }
+    if (st == LB_OK && hipStreamSynchronize(c->stream) != hipSuccess) st = fail(LB_E_HIP, "sync failed");
+    double sum[LB_NPASS] = {0};
+    int cnt[LB_NPASS] = {0};
+    for (size_t k = 0; st == LB_OK && k < h.next; ++k) {
+        float t = 0.f;
+        if (hipEventElapsedTime(&t, h.ev[2 * k], h.ev[2 * k + 1]) != hipSuccess) {
+            st = fail(LB_E_HIP, "hipEventElapsedTime failed");
+            break;
+        }
+        sum[h.kind[k]] += t;
+        cnt[h.kind[k]] += 1;
+    }
+    for (int k = 0; k < LB_NPASS; ++k) ms[k] = cnt[k] ? sum[k] / cnt[k] : 0.0;
+    for (auto e : h.ev)
+        if (e) (void)hipEventDestroy(e);
+    return st;
 }
 
 lb_status lb_sync(lb_ctx* c) {

@@ -11,7 +11,7 @@ import os
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "liblbfft.so")
+LIB_PATH = os.environ.get("LBFFT_LIB", os.path.join(_PKG, "liblbfft.so"))
 
 LB_OK, LB_E_ARG, LB_E_SIZE, LB_E_NOMEM, LB_E_HIP, LB_E_NONFINITE, LB_E_STATE = 0, -1, -2, -3, -4, -5, -6
 LB_FP64, LB_FP32 = 0, 1
@@ -19,8 +19,9 @@ _STATUS = {0: "LB_OK", -1: "LB_E_ARG", -2: "LB_E_SIZE", -3: "LB_E_NOMEM", -4: "L
            -5: "LB_E_NONFINITE", -6: "LB_E_STATE"}
 
 EXPORTS = ("lb_workspace_bytes", "lb_init", "lb_step", "lb_sync", "lb_moments", "lb_conservation",
-           "lb_get_f", "lb_set_f", "lb_force_coefficients", "lb_rhs", "lb_derivative", "lb_free",
-           "lb_last_error")
+           "lb_get_f", "lb_set_f", "lb_force_coefficients", "lb_rhs", "lb_derivative",
+           "lb_step_timed", "lb_free", "lb_last_error")
+PASS_NAMES = ("moments", "macro_x1", "macro_y1", "stress", "macro_x2", "macro_y2", "pop_x", "pop_y")
 
 
 class lb_params(ctypes.Structure):
@@ -68,6 +69,7 @@ def load():
     lib.lb_force_coefficients.argtypes = [V, I, dp, dp, dp]
     lib.lb_rhs.argtypes = [V, I, dp]
     lib.lb_derivative.argtypes = [V, I, I, I, dp, dp]
+    lib.lb_step_timed.argtypes = [V, I, dp]
     lib.lb_free.argtypes = [V]
     lib.lb_free.restype = None
     lib.lb_last_error.restype = ctypes.c_char_p
@@ -180,6 +182,13 @@ def lb_derivative(ctx, inst, axis, order, g):
     return out
 
 
+def lb_step_timed(ctx, n_steps):
+    """Mean milliseconds per launch of each pass kind (dict keyed by PASS_NAMES)."""
+    ms = np.zeros(len(PASS_NAMES))
+    _check(load().lb_step_timed(ctx, n_steps, _dptr(ms)))
+    return dict(zip(PASS_NAMES, ms.tolist()))
+
+
 def lb_free(ctx):
     if ctx:
         load().lb_free(ctx)
@@ -235,6 +244,9 @@ class Sim:
 
     def derivative(self, g, axis, order=1, inst=0):
         return lb_derivative(self.ctx, inst, axis, order, g)
+
+    def step_timed(self, n):
+        return lb_step_timed(self.ctx, n)
 
     def close(self):
         if getattr(self, "ctx", None):

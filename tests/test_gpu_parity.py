@@ -204,3 +204,15 @@ def test_ragged_batch_matches_solo_and_oracle(torch_cuda):
         assert max(errs.values()) < 1e-12
         solo.close()
     sim.close()
+
+
+def test_step_timed_matches_graph_step(torch_cuda):
+    p = W.base_params()
+    ic = W.quench(64, 48, 0.52, 9)
+    a, b = _sim([(p, ic)]), _sim([(p, ic)], )
+    a.step(4)
+    ms = b.step_timed(4)
+    assert all(v > 0 for v in ms.values()), ms
+    assert np.array_equal(a.get_f(), b.get_f())
+    a.close()
+    b.close()
