@@ -82,13 +82,14 @@ def run_gpu(instances, precision, steps, warmup, timed_steps):
     t1 = time.perf_counter()
     passes = sim.step_timed(timed_steps)
     sim.sync()
+    plan = sim.plan(0)
     c = sim.conservation(0)
     sim.close()
     if not np.all(np.isfinite(c)):
         raise RuntimeError("non-finite state after the benchmark")
     dt = t1 - t0
     return dict(mlups=cells * steps / dt / 1e6, ms_per_step=1e3 * dt / steps, cells=cells,
-                passes=passes)
+                passes=passes, plan=plan)
 
 
 def roofline(res, word_bytes, workload):
@@ -131,6 +132,17 @@ def cpu_baseline(instances, budget_s=15.0):
                        f"warm-up step, scipy.fft workers={workers}")
 
 
+def calib_copy():
+    """A plain device copy of exactly 256 MiB (read 256 MiB, write 256 MiB), three times: the
+    reference dispatch for scaling the HBM byte counters."""
+    import torch
+    src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -139,6 +151,10 @@ def main():
     ap.add_argument("--timed-steps", type=int, default=50)
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--only", choices=("quench512_fp64", "quench512_fp32", "batch128x256_fp32"),
+                    help="run one workload only and print its summary (for profiling)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="finish with a 256 MiB device-to-device copy (HBM counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark runs on one GPU only; multi-GPU sharding is a "
@@ -146,6 +162,17 @@ def main():
         sys.exit(2)
 
     from paper_1403_3746_amd import workloads as W
+
+    if args.only:
+        name, prec = args.only.rsplit("_", 1)
+        insts, _ = W.config(name)
+        r = run_gpu(insts, prec, args.steps, args.warmup, args.timed_steps)
+        print(json.dumps({"workload": args.only, "mlups": round(r["mlups"], 2),
+                          "ms_per_step": round(r["ms_per_step"], 5), "plan": r["plan"],
+                          "roofline": roofline(r, 8 if prec == "fp64" else 4, args.only)}))
+        if args.calib_copy:
+            calib_copy()
+        return
 
     insts, _ = W.config("quench512")
     main_res = run_gpu(insts, "fp64", args.steps, args.warmup, args.timed_steps)
@@ -166,17 +193,19 @@ def main():
                    "grid": [512, 512], "instances": 1, "precision": "fp64",
                    "params": "dx=1 dt=1e-3 tau=1e-2 K=1e-2 a=9/49 b_w=2/21 T=0.9T_c b=2 H=zeta=q=0"},
         "roofline": roofline(main_res, 8, "quench512_fp64"),
+        "plan": main_res["plan"],
     }
     if not args.no_variants:
         var = {}
         r32 = run_gpu(insts, "fp32", args.steps, args.warmup, args.timed_steps)
         var["quench512_fp32"] = dict(mlups=round(r32["mlups"], 2), ms_per_step=round(r32["ms_per_step"], 5),
-                                     roofline=roofline(r32, 4, "quench512_fp32"))
+                                     roofline=roofline(r32, 4, "quench512_fp32"), plan=r32["plan"])
         binsts, _ = W.config("batch128x256")
         bsteps = max(1, args.steps // 4)
         rb = run_gpu(binsts, "fp32", bsteps, max(1, args.warmup // 4), max(1, args.timed_steps // 4))
         var["batch128x256_fp32"] = dict(mlups=round(rb["mlups"], 2), ms_per_step=round(rb["ms_per_step"], 5),
-                                        steps=bsteps, roofline=roofline(rb, 4, "batch128x256_fp32"))
+                                        steps=bsteps, roofline=roofline(rb, 4, "batch128x256_fp32"),
+                                        plan=rb["plan"])
         var["fp32_batched_over_fp64_plain"] = round(rb["mlups"] / main_res["mlups"], 3)
         out["variants"] = var
     if not args.no_cpu:

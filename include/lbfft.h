@@ -150,6 +150,11 @@ enum {
  * lb_step.  For measurement only. */
 lb_status lb_step_timed(lb_ctx* ctx, int n_steps, double ms[LB_NPASS]);
 
+/* Launch plan chosen for instance inst's size class at lb_init (measured on the instance's
+ * data unless the environment sets LBFFT_TUNE=0):  out[0] = populations per block of the x
+ * population pass (1, 2 or 4), out[1] = size classes in the context.  n = length of out (>= 2). */
+lb_status lb_plan_info(lb_ctx* ctx, int inst, int* out, int n);
+
 /* Release the context (not the caller's workspace).  NULL is ignored. */
 void lb_free(lb_ctx* ctx);
 

@@ -9,12 +9,25 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+// Global-memory pointers: pointers read out of descriptors are otherwise generic (flat), and flat
+// accesses also hold the LDS wait counter, which stalls the FFT's LDS exchanges on field loads.
+#define LB_GLOBAL __attribute__((address_space(1)))
+
 namespace lbfft {
 
 template <typename T>
 struct cpx {
     T re, im;
 };
+
+template <typename T>
+__device__ __forceinline__ const LB_GLOBAL T* gcast(const T* p) {
+    return (const LB_GLOBAL T*)p;
+}
+template <typename T>
+__device__ __forceinline__ LB_GLOBAL T* gcast(T* p) {
+    return (LB_GLOBAL T*)p;
+}
 
 template <typename T>
 __device__ __forceinline__ cpx<T> cadd(cpx<T> a, cpx<T> b) { return {a.re + b.re, a.im + b.im}; }
@@ -166,14 +179,41 @@ __host__ __device__ constexpr int lds_idx(int i) { return i + (i >> LDS_PAD_SHIF
 __host__ __device__ constexpr int lds_line(int N) { return N + (N >> LDS_PAD_SHIFT) + 1; }
 
 template <typename T>
-__device__ __forceinline__ cpx<T> ld_tw(const cpx<T>* __restrict__ tw, int idx) {
-    return tw[idx];
+using twptr = const LB_GLOBAL cpx<T>*;
+
+// Complex load from global memory (member-wise: no copy constructor across address spaces).
+template <typename T>
+__device__ __forceinline__ cpx<T> ldc(twptr<T> p, int idx) {
+    return cpx<T>{p[idx].re, p[idx].im};
+}
+
+// Twiddles w^q, q = 1..r-1, of base index `step` (w^q = tw[q*step]).  Radix 8 loads w, w^2, w^4
+// and forms the rest by at most two products; radix 4 loads w, w^2; radix 2, 3 load directly.
+template <typename T, int r, bool INV>
+__device__ __forceinline__ void twiddle_powers(twptr<T> tw, int step, cpx<T>* w) {
+    if constexpr (r == 8) {
+        w[1] = ldc(tw, step);
+        w[2] = ldc(tw, 2 * step);
+        w[4] = ldc(tw, 4 * step);
+        w[3] = cmul(w[1], w[2]);
+        w[5] = cmul(w[4], w[1]);
+        w[6] = cmul(w[4], w[2]);
+        w[7] = cmul(w[4], w[3]);
+    } else if constexpr (r == 4) {
+        w[1] = ldc(tw, step);
+        w[2] = ldc(tw, 2 * step);
+        w[3] = cmul(w[1], w[2]);
+    } else {
+#pragma unroll
+        for (int q = 1; q < r; ++q) w[q] = ldc(tw, q * step);
+    }
 }
 
 // One Stockham pass of radix r with Ns = product of the previous radices.
-template <typename T, int N, int R, int r, int Ns, bool INV, bool FROM_REG, bool TO_REG>
-__device__ __forceinline__ void stockham_pass(cpx<T> (&v)[R], cpx<T>* lds, int t,
-                                              const cpx<T>* __restrict__ tw) {
+// LDS element i of the line lives at lds[lds_idx(i) * LS]: LS = 1 for line-contiguous storage,
+// LS = lines per block for lines interleaved word by word (lanes of neighbouring lines adjacent).
+template <typename T, int N, int R, int r, int Ns, bool INV, bool FROM_REG, bool TO_REG, int LS>
+__device__ __forceinline__ void stockham_pass(cpx<T> (&v)[R], cpx<T>* lds, int t, twptr<T> tw) {
     constexpr int TPL = N / R;
     constexpr int NB = R / r;
     static_assert(R % r == 0, "radix must divide R");
@@ -187,7 +227,7 @@ __device__ __forceinline__ void stockham_pass(cpx<T> (&v)[R], cpx<T>* lds, int t
         for (int b = 0; b < NB; ++b) {
             const int j = t + b * TPL;
 #pragma unroll
-            for (int q = 0; q < r; ++q) a[b * r + q] = lds[lds_idx(j + q * (N / r))];
+            for (int q = 0; q < r; ++q) a[b * r + q] = lds[lds_idx(j + q * (N / r)) * LS];
         }
         __syncthreads();
     }
@@ -196,11 +236,10 @@ __device__ __forceinline__ void stockham_pass(cpx<T> (&v)[R], cpx<T>* lds, int t
         const int j = t + b * TPL;
         const int k = j % Ns;
         if constexpr (Ns > 1) {
+            cpx<T> w[r];
+            twiddle_powers<T, r, INV>(tw, k * (N / (Ns * r)), w);
 #pragma unroll
-            for (int q = 1; q < r; ++q) {
-                const cpx<T> w = ld_tw(tw, k * q * (N / (Ns * r)));
-                a[b * r + q] = INV ? cmulc(a[b * r + q], w) : cmul(a[b * r + q], w);
-            }
+            for (int q = 1; q < r; ++q) a[b * r + q] = INV ? cmulc(a[b * r + q], w[q]) : cmul(a[b * r + q], w[q]);
         }
         Dft<T, r, INV>::run(&a[b * r]);
         if constexpr (TO_REG) {
@@ -210,20 +249,19 @@ __device__ __forceinline__ void stockham_pass(cpx<T> (&v)[R], cpx<T>* lds, int t
         } else {
             const int base = (j / Ns) * Ns * r + k;
 #pragma unroll
-            for (int q = 0; q < r; ++q) lds[lds_idx(base + q * Ns)] = a[b * r + q];
+            for (int q = 0; q < r; ++q) lds[lds_idx(base + q * Ns) * LS] = a[b * r + q];
         }
     }
     if constexpr (!TO_REG) __syncthreads();
 }
 
-template <typename T, int N, int R, bool INV>
+template <typename T, int N, int R, bool INV, int LS = 1>
 struct LineFFT {
     static constexpr Plan P = make_plan(N, R);
     static constexpr int TPL = N / R;
 
     template <int s>
-    __device__ __forceinline__ static void passes(cpx<T> (&v)[R], cpx<T>* lds, int t,
-                                                  const cpx<T>* __restrict__ tw) {
+    __device__ __forceinline__ static void passes(cpx<T> (&v)[R], cpx<T>* lds, int t, twptr<T> tw) {
         if constexpr (s < P.np) {
             constexpr int r = P.r[s];
             constexpr int Ns = plan_ns(P, s);
@@ -231,15 +269,14 @@ struct LineFFT {
             constexpr bool last = (s == P.np - 1);
             constexpr bool from_reg = first && (r == R);
             constexpr bool to_reg = last && (r == R);
-            stockham_pass<T, N, R, r, Ns, INV, from_reg, to_reg>(v, lds, t, tw);
+            stockham_pass<T, N, R, r, Ns, INV, from_reg, to_reg, LS>(v, lds, t, tw);
             passes<s + 1>(v, lds, t, tw);
         }
     }
 
     // Transform the line in place: v[m] = x[t + m*TPL] on entry, X[t + m*TPL] on exit.
     // All threads of the workgroup must call this together (it contains barriers).
-    __device__ __forceinline__ static void run(cpx<T> (&v)[R], cpx<T>* lds, int t,
-                                               const cpx<T>* __restrict__ tw) {
+    __device__ __forceinline__ static void run(cpx<T> (&v)[R], cpx<T>* lds, int t, twptr<T> tw) {
         if constexpr (P.np == 0) {
             return;
         } else {
@@ -247,13 +284,13 @@ struct LineFFT {
             constexpr bool last_reg = (P.r[P.np - 1] == R);
             if constexpr (!first_reg) {
 #pragma unroll
-                for (int m = 0; m < R; ++m) lds[lds_idx(t + m * TPL)] = v[m];
+                for (int m = 0; m < R; ++m) lds[lds_idx(t + m * TPL) * LS] = v[m];
                 __syncthreads();
             }
             passes<0>(v, lds, t, tw);
             if constexpr (!last_reg) {
 #pragma unroll
-                for (int m = 0; m < R; ++m) v[m] = lds[lds_idx(t + m * TPL)];
+                for (int m = 0; m < R; ++m) v[m] = lds[lds_idx(t + m * TPL) * LS];
             }
             // the next transform may write LDS that slower threads are still reading
             if constexpr (!(P.np == 1 && first_reg && last_reg)) __syncthreads();

@@ -21,6 +21,9 @@
 #ifndef LB_EPI_GROUP
 #define LB_EPI_GROUP 4   // epilogue positions whose field loads may be hoisted together
 #endif
+#ifndef LB_POPX_WAVES
+#define LB_POPX_WAVES 4  // waves per SIMD the single-population x pass must fit (register budget)
+#endif
 
 namespace lbfft {
 
@@ -28,6 +31,8 @@ namespace lbfft {
 // Launch geometry of the line passes.  Small tiles keep many blocks in flight for a single grid;
 // y tiles span LPW column pairs (2*LPW*sizeof(T) bytes of each row), and neighbouring tiles run
 // on the same XCD (see decode_block) so partially used cache lines are reused from L2.
+// LDS: x blocks (lanes of one line adjacent) store each line contiguously; y blocks (lanes of
+// neighbouring lines adjacent) interleave their lines word by word (LS = LPW).
 template <typename T, int N, int DIR>
 struct LineCfg {
     static constexpr int R = default_R(N);
@@ -36,14 +41,17 @@ struct LineCfg {
     static constexpr int at_least(int l, int lo) { return l < lo ? lo : l; }
     // x: one line per block unless lines are short (then fill one wave)
     static constexpr int lpw_x() { return at_least(64 / TPL, 1); }
-    // y: 32-byte row segments, at least one wave per block
+    // y: 32-byte row segments, at least one wave per block, at most 512 threads
     static constexpr int lpw_y() {
         int l = at_least(at_least(32 / CB, 64 / TPL), 1);
-        return (l * TPL > 512) ? at_least(512 / TPL, 1) : l;   // cap the block at 512 threads
+        return (l * TPL > 512) ? at_least(512 / TPL, 1) : l;
     }
     static constexpr int LPW = DIR == 0 ? lpw_x() : lpw_y();
     static constexpr int WG = LPW * TPL;
+    static constexpr int LS = DIR == 0 ? 1 : LPW;
     static constexpr int LDS = LPW * lds_line(N);   // complex words
+    // LDS base of line l of the block
+    __device__ __forceinline__ static int lds_base(int l) { return DIR == 0 ? l * lds_line(N) : l; }
 };
 
 // Decode the flat block index into (instance, tile, job).  Workgroups are dealt to the 8 XCDs
@@ -92,21 +100,27 @@ struct vec2 {
     T a, b;
 };
 
+// Field `id` of an instance as a global-memory pointer (cells indexed by 32-bit offsets).
+template <typename T>
+__device__ __forceinline__ LB_GLOBAL T* fieldp(const InstDesc& I, int id) {
+    return gcast(reinterpret_cast<T*>(I.base) + (int64_t)id * I.ncell);
+}
+
 // Addressing of the two real lines packed into complex line `line` at position p.
 template <int DIR>
 struct LineAddr {
-    // element index of the real part (re) and imaginary part (im) of position p
-    __device__ __forceinline__ static int64_t re(int line, int p, int nx) {
-        return DIR == 0 ? (int64_t)(2 * line) * nx + p : (int64_t)p * nx + 2 * line;
+    // cell index of the real part (re) and imaginary part (im) of position p
+    __device__ __forceinline__ static uint32_t re(int line, int p, int nx) {
+        return DIR == 0 ? (uint32_t)(2 * line) * nx + p : (uint32_t)p * nx + 2 * line;
     }
-    __device__ __forceinline__ static int64_t im(int line, int p, int nx) {
-        return DIR == 0 ? (int64_t)(2 * line + 1) * nx + p : (int64_t)p * nx + 2 * line + 1;
+    __device__ __forceinline__ static uint32_t im(int line, int p, int nx) {
+        return DIR == 0 ? (uint32_t)(2 * line + 1) * nx + p : (uint32_t)p * nx + 2 * line + 1;
     }
 };
 
 template <typename T, int DIR, int R, int TPL>
-__device__ __forceinline__ void load_line(const T* __restrict__ g, cpx<T> (&v)[R], int line,
-                                          int t, int nx, int ny, bool active) {
+__device__ __forceinline__ void load_line(const LB_GLOBAL T* g, cpx<T> (&v)[R], int line, int t,
+                                          int nx, int ny, bool active) {
 #pragma unroll
     for (int m = 0; m < R; ++m) {
         const int p = t + m * TPL;
@@ -116,9 +130,9 @@ __device__ __forceinline__ void load_line(const T* __restrict__ g, cpx<T> (&v)[R
                 z.re = g[LineAddr<0>::re(line, p, nx)];
                 if (2 * line + 1 < ny) z.im = g[LineAddr<0>::im(line, p, nx)];
             } else {
-                const vec2<T> w = *reinterpret_cast<const vec2<T>*>(g + LineAddr<1>::re(line, p, nx));
-                z.re = w.a;
-                z.im = w.b;
+                const LB_GLOBAL vec2<T>* w = reinterpret_cast<const LB_GLOBAL vec2<T>*>(g + LineAddr<1>::re(line, p, nx));
+                z.re = w->a;
+                z.im = w->b;
             }
         }
         v[m] = z;
@@ -132,6 +146,8 @@ __global__ void __launch_bounds__((LineCfg<T, N, DIR>::WG))
 macro_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, int ngroups,
            int ntiles, const JobDesc* __restrict__ jobs, int njobs) {
     using C = LineCfg<T, N, DIR>;
+    using FFT = LineFFT<T, N, C::R, false, C::LS>;
+    using IFFT = LineFFT<T, N, C::R, true, C::LS>;
     constexpr int R = C::R, TPL = C::TPL, LPW = C::LPW;
     __shared__ cpx<T> lds_all[C::LDS];
     const BlockWork w = decode_block(ngroups, ntiles, njobs);
@@ -147,16 +163,14 @@ macro_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
     const int nx = I.nx, ny = I.ny;
     const int nlines = DIR == 0 ? (ny + 1) / 2 : nx / 2;
     const bool active = line < nlines;
-    cpx<T>* lds = lds_all + l * lds_line(N);
-    T* fld = reinterpret_cast<T*>(I.base);
-    const int64_t nc = I.ncell;
-    const T* __restrict__ kap = reinterpret_cast<const T*>(DIR == 0 ? I.kx : I.ky);
-    const cpx<T>* __restrict__ tw = reinterpret_cast<const cpx<T>*>(DIR == 0 ? I.twx : I.twy);
+    cpx<T>* lds = lds_all + C::lds_base(l);
+    const LB_GLOBAL T* kap = gcast(reinterpret_cast<const T*>(DIR == 0 ? I.kx : I.ky));
+    const twptr<T> tw = gcast(reinterpret_cast<const cpx<T>*>(DIR == 0 ? I.twx : I.twy));
 
     // spectrum of the first input
     cpx<T> X[R], Y[R];
-    load_line<T, DIR, R, TPL>(fld + J.in[0] * nc, X, line, t, nx, ny, active);
-    LineFFT<T, N, R, false>::run(X, lds, t, tw);
+    load_line<T, DIR, R, TPL>(fieldp<T>(I, J.in[0]), X, line, t, nx, ny, active);
+    FFT::run(X, lds, t, tw);
     const T invN = T(1.0 / N);
     const bool two = J.in[1] >= 0;   // two inputs: a single output from the summed spectra
 #pragma unroll 1
@@ -173,17 +187,21 @@ macro_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
         for (int m = 0; m < R; ++m) Y[m] = spectral_mult<T>(mk0, kap[t + m * TPL], invN, X[m]);
         if (two) {
             // X is no longer needed: transform the second input in its place
-            load_line<T, DIR, R, TPL>(fld + J.in[1] * nc, X, line, t, nx, ny, active);
-            LineFFT<T, N, R, false>::run(X, lds, t, tw);
+            load_line<T, DIR, R, TPL>(fieldp<T>(I, J.in[1]), X, line, t, nx, ny, active);
+            FFT::run(X, lds, t, tw);
 #pragma unroll
             for (int m = 0; m < R; ++m) {
                 const cpx<T> z = spectral_mult<T>(mk1, kap[t + m * TPL], invN, X[m]);
                 Y[m] = cadd(Y[m], z);
             }
         }
-        LineFFT<T, N, R, true>::run(Y, lds, t, tw);
+        IFFT::run(Y, lds, t, tw);
         if (!active) continue;
-        T* __restrict__ out = fld + outf * nc;
+        LB_GLOBAL T* out = fieldp<T>(I, outf);
+        const LB_GLOBAL T* prep = fieldp<T>(I, pre < 0 ? 0 : pre);
+        const LB_GLOBAL T* postp = fieldp<T>(I, post < 0 ? 0 : post);
+        const LB_GLOBAL T* rhop = fieldp<T>(I, RHO);
+        const LB_GLOBAL T* tp = fieldp<T>(I, TT);
 #pragma unroll
         for (int m = 0; m < R; ++m) {
             // compiler fence: bounds how many epilogue loads are hoisted (register pressure)
@@ -192,14 +210,14 @@ macro_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
 #pragma unroll
             for (int h = 0; h < 2; ++h) {
                 if (DIR == 0 && h == 1 && 2 * line + 1 >= ny) continue;
-                const int64_t e = h == 0 ? LineAddr<DIR>::re(line, p, nx) : LineAddr<DIR>::im(line, p, nx);
+                const uint32_t e = h == 0 ? LineAddr<DIR>::re(line, p, nx) : LineAddr<DIR>::im(line, p, nx);
                 T val = h == 0 ? Y[m].re : Y[m].im;
-                if (pre >= 0) val += fld[pre * nc + e];
+                if (pre >= 0) val += prep[e];
                 if (sc != S_ONE) {
-                    const T rho = fld[RHO * nc + e], T_ = fld[TT * nc + e];
+                    const T rho = rhop[e], T_ = tp[e];
                     val = sc == S_INV_RHOT ? val / (rho * T_) : val / (rho * T_ * T_);
                 }
-                if (post >= 0) val += fld[post * nc + e];
+                if (post >= 0) val += postp[e];
                 out[e] = val;
             }
         }
@@ -209,76 +227,109 @@ macro_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
 
 // ---------------------------------------------------------------------------------------
 // Equilibrium f_i^eq of the seven kinetic moments: f^eq = C^{-1} M^eq(rho, u, T).
+// meq_unit fills m[j] = M^eq_j / rho (the Maxwellian moments per unit density, Sec. 2.2).
 template <typename T>
-__device__ __forceinline__ T feq_pop(const DvmConst<T>& D, int i, T rho, T ux, T uy, T Tm, T b) {
+__device__ __forceinline__ void meq_unit(T ux, T uy, T Tm, T b, T (&m)[16]) {
     const T u2 = ux * ux + uy * uy;
     const T h2 = (b + T(2)) * Tm + u2;
     const T h4 = (b + T(4)) * Tm + u2;
-    const T m[16] = {T(1), ux, uy, b * Tm + u2,
-                     Tm + ux * ux, ux * uy, Tm + uy * uy,
-                     ux * h2, uy * h2,
-                     T(3) * Tm * ux + ux * ux * ux, Tm * uy + ux * ux * uy,
-                     Tm * ux + ux * uy * uy, T(3) * Tm * uy + uy * uy * uy,
-                     h2 * Tm + h4 * ux * ux, h4 * ux * uy, h2 * Tm + h4 * uy * uy};
+    m[0] = T(1);
+    m[1] = ux;
+    m[2] = uy;
+    m[3] = b * Tm + u2;
+    m[4] = Tm + ux * ux;
+    m[5] = ux * uy;
+    m[6] = Tm + uy * uy;
+    m[7] = ux * h2;
+    m[8] = uy * h2;
+    m[9] = T(3) * Tm * ux + ux * ux * ux;
+    m[10] = Tm * uy + ux * ux * uy;
+    m[11] = Tm * ux + ux * uy * uy;
+    m[12] = T(3) * Tm * uy + uy * uy * uy;
+    m[13] = h2 * Tm + h4 * ux * ux;
+    m[14] = h4 * ux * uy;
+    m[15] = h2 * Tm + h4 * uy * uy;
+}
+
+template <typename T>
+__device__ __forceinline__ T feq_dot(const DvmConst<T>& D, int i, T rho, const T (&m)[16]) {
     T s = T(0);
 #pragma unroll
     for (int j = 0; j < 16; ++j) s += D.cinv[i][j] * m[j];
     return rho * s;
 }
 
+template <typename T>
+__device__ __forceinline__ T feq_pop(const DvmConst<T>& D, int i, T rho, T ux, T uy, T Tm, T b) {
+    T m[16];
+    meq_unit(ux, uy, Tm, b, m);
+    return feq_dot(D, i, rho, m);
+}
+
 // ---------------------------------------------------------------------------------------
-// Population x pass: one block = (instance, tile of row pairs, population i).
-//   partial = base + c [ -v_x D_x f - (f - f^eq)/tau + I ]          (written to F_P + i)
-//   axis-x populations (v_y = 0) are final and go to out_field + i.
-template <typename T, int N>
+// Population x pass: one block = (instance, tile of row pairs, P populations).  For each
+// population i of the block (D.xorder[job*P + q]):
+//   out = base + c [ -v_x D_x f - (f - f^eq)/tau + I ]
+// to out_field + i if v_y = 0 (final) or to the partial block F_P + i otherwise.  The terms
+// linear in f, -c v_x D_x f - (c/tau) f, are one spectral multiplier (-c/tau + i (-c v_x k))/N;
+// the equilibrium moments and the coefficient loads of a cell are shared by the P populations.
+template <typename T, int N, int P>
 __global__ void __launch_bounds__((LineCfg<T, N, 0>::WG))
+__attribute__((amdgpu_waves_per_eu(LB_POPX_WAVES / P > 1 ? LB_POPX_WAVES / P : 1)))
 pop_x_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, int ngroups,
            int ntiles, const DvmConst<T>* __restrict__ dvm, StageArgs st) {
     using C = LineCfg<T, N, 0>;
     constexpr int R = C::R, TPL = C::TPL;
     __shared__ cpx<T> lds_all[C::LDS];
-    const BlockWork w = decode_block(ngroups, ntiles, 16);
+    const BlockWork w = decode_block(ngroups, ntiles, 16 / P);
     if (!w.valid) return;
     const InstDesc& I = insts[ilist[w.inst_local]];
     const DvmConst<T>& D = *dvm;
-    const int i = w.job;
     const int tid = threadIdx.x;
     const int l = tid / TPL, t = tid % TPL;
     const int line = w.tile * C::LPW + l;
     const int nx = I.nx, ny = I.ny;
     const bool active = line < (ny + 1) / 2;
-    cpx<T>* lds = lds_all + l * lds_line(N);
-    T* fld = reinterpret_cast<T*>(I.base);
-    const int64_t nc = I.ncell;
-    const T vx = D.vx[i], vy = D.vy[i];
+    cpx<T>* lds = lds_all + C::lds_base(l);
     const T c = T(st.use_dt ? st.alpha * I.dt : st.alpha);
+    const T inv_tau = T(1.0 / I.tau);
+    const T ct = c * inv_tau;
+    const twptr<T> tw = gcast(reinterpret_cast<const cpx<T>*>(I.twx));
+    const LB_GLOBAL T* kap = gcast(reinterpret_cast<const T*>(I.kx));
+    const T invN = T(1.0 / N);
 
-    cpx<T> F[R], X[R];
-    load_line<T, 0, R, TPL>(fld + (st.f_field + i) * nc, F, line, t, nx, ny, active);
-    if (vx != T(0)) {
+    // X[q] <- -c v_x D_x f_i - (c/tau) f_i on the block's two rows
+    cpx<T> X[P][R];
 #pragma unroll
-        for (int m = 0; m < R; ++m) X[m] = F[m];
-        LineFFT<T, N, R, false>::run(X, lds, t, reinterpret_cast<const cpx<T>*>(I.twx));
-        const T* __restrict__ kap = reinterpret_cast<const T*>(I.kx);
-        const T s = -c * vx * T(1.0 / N);
+    for (int q = 0; q < P; ++q) {
+        const int i = D.xorder[w.job * P + q];
+        const T vx = D.vx[i];
+        load_line<T, 0, R, TPL>(fieldp<T>(I, st.f_field + i), X[q], line, t, nx, ny, active);
+        if (vx != T(0)) {
+            LineFFT<T, N, R, false>::run(X[q], lds, t, tw);
+            const T s = -c * vx * invN, mr = -ct * invN;
 #pragma unroll
-        for (int m = 0; m < R; ++m) {
-            const T a = s * kap[t + m * TPL];
-            const cpx<T> x = X[m];
-            X[m] = {-a * x.im, a * x.re};
+            for (int m = 0; m < R; ++m) {
+                const T mi = s * kap[t + m * TPL];
+                const cpx<T> x = X[q][m];
+                X[q][m] = {mr * x.re - mi * x.im, mr * x.im + mi * x.re};
+            }
+            LineFFT<T, N, R, true>::run(X[q], lds, t, tw);
+        } else {
+#pragma unroll
+            for (int m = 0; m < R; ++m) X[q][m] = {-ct * X[q][m].re, -ct * X[q][m].im};
         }
-        LineFFT<T, N, R, true>::run(X, lds, t, reinterpret_cast<const cpx<T>*>(I.twx));
-    } else {
-#pragma unroll
-        for (int m = 0; m < R; ++m) X[m] = {T(0), T(0)};
     }
     if (!active) return;
-    const T inv_tau = T(1.0 / I.tau), b = T(I.b);
-    const int ct = I.q != 0.0 ? CT : C0;
-    const bool final_here = (vy == T(0));
-    // out may equal the base block (second stage writes f^{n+1} over f^n cell by cell): no restrict
-    T* out = fld + ((final_here ? st.out_field : F_P) + i) * nc;
-    const T* basep = st.base_field >= 0 ? fld + (st.base_field + i) * nc : nullptr;
+    const T b = T(I.b);
+    const bool has_base = st.base_field >= 0;
+    const LB_GLOBAL T* rhop = fieldp<T>(I, RHO);
+    const LB_GLOBAL T* uxp = fieldp<T>(I, UX);
+    const LB_GLOBAL T* uyp = fieldp<T>(I, UY);
+    const LB_GLOBAL T* tp = fieldp<T>(I, TT);
+    const LB_GLOBAL T* bxp = fieldp<T>(I, BX);
+    const LB_GLOBAL T* byp = fieldp<T>(I, BY);
+    const LB_GLOBAL T* dcp = fieldp<T>(I, I.q != 0.0 ? CT : C0);
 #pragma unroll
     for (int m = 0; m < R; ++m) {
         if (m % LB_EPI_GROUP == 0) asm volatile("" ::: "memory");
@@ -286,18 +337,26 @@ pop_x_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
 #pragma unroll
         for (int h = 0; h < 2; ++h) {
             if (h == 1 && 2 * line + 1 >= ny) continue;
-            const int64_t e = (int64_t)(2 * line + h) * nx + p;
-            const T rho = fld[RHO * nc + e], ux = fld[UX * nc + e], uy = fld[UY * nc + e];
-            const T Tm = fld[TT * nc + e];
-            const T Bx = fld[BX * nc + e], By = fld[BY * nc + e], Dc = fld[ct * nc + e];
-            const T fv = h == 0 ? F[m].re : F[m].im;
-            const T dv = h == 0 ? X[m].re : X[m].im;
-            const T fe = feq_pop(D, i, rho, ux, uy, Tm, b);
-            const T cx = vx - ux, cy = vy - uy;
-            const T A = T(-2) * Dc * Tm;
-            const T force = -(A + Bx * cx + By * cy + Dc * (cx * cx + cy * cy)) * fe;
-            const T base = basep ? basep[e] : T(0);
-            out[e] = base + dv + c * (force - (fv - fe) * inv_tau);
+            const uint32_t e = (uint32_t)(2 * line + h) * nx + p;
+            const T rho = rhop[e], ux = uxp[e], uy = uyp[e], Tm = tp[e];
+            const T Bx = bxp[e], By = byp[e], Dc = dcp[e];
+            T mq[16];
+            meq_unit(ux, uy, Tm, b, mq);
+            // I_i = -[A + B.(v_i - u) + D |v_i - u|^2] f^eq_i with A = -2 D T
+            const T g0 = T(-2) * Dc * Tm;
+#pragma unroll
+            for (int q = 0; q < P; ++q) {
+                const int i = D.xorder[w.job * P + q];
+                const T vx = D.vx[i], vy = D.vy[i];
+                const T fe = feq_dot(D, i, rho, mq);
+                const T cx = vx - ux, cy = vy - uy;
+                const T force = -(g0 + Bx * cx + By * cy + Dc * (cx * cx + cy * cy)) * fe;
+                const T lin = h == 0 ? X[q][m].re : X[q][m].im;
+                const T base = has_base ? fieldp<T>(I, st.base_field + i)[e] : T(0);
+                // out may equal the base block (second stage writes f^{n+1} over f^n per cell)
+                LB_GLOBAL T* out = fieldp<T>(I, (vy == T(0) ? st.out_field : F_P) + i);
+                out[e] = base + lin + c * (force + fe * inv_tau);
+            }
         }
     }
 }
@@ -321,15 +380,14 @@ pop_y_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
     const int line = w.tile * LPW + l;
     const int nx = I.nx, ny = I.ny;
     const bool active = line < nx / 2;
-    cpx<T>* lds = lds_all + l * lds_line(N);
-    T* fld = reinterpret_cast<T*>(I.base);
-    const int64_t nc = I.ncell;
+    cpx<T>* lds = lds_all + C::lds_base(l);
     const T vy = dvm->vy[i];
+    const twptr<T> tw = gcast(reinterpret_cast<const cpx<T>*>(I.twy));
 
     cpx<T> X[R];
-    load_line<T, 1, R, TPL>(fld + (st.f_field + i) * nc, X, line, t, nx, ny, active);
-    LineFFT<T, N, R, false>::run(X, lds, t, reinterpret_cast<const cpx<T>*>(I.twy));
-    const T* __restrict__ kap = reinterpret_cast<const T*>(I.ky);
+    load_line<T, 1, R, TPL>(fieldp<T>(I, st.f_field + i), X, line, t, nx, ny, active);
+    LineFFT<T, N, R, false, C::LS>::run(X, lds, t, tw);
+    const LB_GLOBAL T* kap = gcast(reinterpret_cast<const T*>(I.ky));
     const T s = -T(st.use_dt ? st.alpha * I.dt : st.alpha) * vy * T(1.0 / N);
 #pragma unroll
     for (int m = 0; m < R; ++m) {
@@ -337,30 +395,28 @@ pop_y_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
         const cpx<T> x = X[m];
         X[m] = {-a * x.im, a * x.re};
     }
-    LineFFT<T, N, R, true>::run(X, lds, t, reinterpret_cast<const cpx<T>*>(I.twy));
+    LineFFT<T, N, R, true, C::LS>::run(X, lds, t, tw);
     if (!active) return;
-    const T* __restrict__ part = fld + (F_P + i) * nc;
-    T* __restrict__ out = fld + (st.out_field + i) * nc;
+    const LB_GLOBAL T* part = fieldp<T>(I, F_P + i);
+    LB_GLOBAL T* out = fieldp<T>(I, st.out_field + i);
 #pragma unroll
     for (int m = 0; m < R; ++m) {
         const int p = t + m * TPL;
-        const int64_t e = LineAddr<1>::re(line, p, nx);
-        const vec2<T> pv = *reinterpret_cast<const vec2<T>*>(part + e);
-        vec2<T> o;
-        o.a = pv.a + X[m].re;
-        o.b = pv.b + X[m].im;
-        *reinterpret_cast<vec2<T>*>(out + e) = o;
+        const uint32_t e = LineAddr<1>::re(line, p, nx);
+        const LB_GLOBAL vec2<T>* pv = reinterpret_cast<const LB_GLOBAL vec2<T>*>(part + e);
+        const T a = pv->a + X[m].re, b = pv->b + X[m].im;
+        LB_GLOBAL vec2<T>* o = reinterpret_cast<LB_GLOBAL vec2<T>*>(out + e);
+        o->a = a;
+        o->b = b;
     }
 }
 
 // ---------------------------------------------------------------------------------------
 // Pointwise kernels: grid = (cell chunks, instances in the launch).
-#define LB_POINTWISE_PROLOGUE                                       \
-    const InstDesc& I = insts[ilist[blockIdx.y]];                   \
-    const int64_t nc = I.ncell;                                     \
-    const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; \
-    if (e >= nc) return;                                            \
-    T* fld = reinterpret_cast<T*>(I.base);
+#define LB_POINTWISE_PROLOGUE                                        \
+    const InstDesc& I = insts[ilist[blockIdx.y]];                    \
+    const uint32_t e = blockIdx.x * blockDim.x + threadIdx.x;        \
+    if (e >= (uint32_t)I.ncell) return;
 
 // Moments of Sec. 2.1: rho = sum f, rho u = sum f v, rho (b T + u^2) = sum f (v^2 + eta^2).
 template <typename T>
@@ -372,17 +428,17 @@ moments_kernel(const InstDesc* __restrict__ insts, const int* __restrict__ ilist
     T r = 0, jx = 0, jy = 0, en = 0;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-        const T f = fld[(f_field + i) * nc + e];
+        const T f = fieldp<T>(I, f_field + i)[e];
         r += f;
         jx += f * D.vx[i];
         jy += f * D.vy[i];
         en += f * D.w[i];
     }
     const T ux = jx / r, uy = jy / r;
-    fld[RHO * nc + e] = r;
-    fld[UX * nc + e] = ux;
-    fld[UY * nc + e] = uy;
-    fld[TT * nc + e] = (en / r - ux * ux - uy * uy) / T(I.b);
+    fieldp<T>(I, RHO)[e] = r;
+    fieldp<T>(I, UX)[e] = ux;
+    fieldp<T>(I, UY)[e] = uy;
+    fieldp<T>(I, TT)[e] = (en / r - ux * ux - uy * uy) / T(I.b);
 }
 
 // Stress S = (P^w - rho T) I + Lambda - zeta (div u) I, the C of Eq. (2) without C_q, and
@@ -391,12 +447,12 @@ template <typename T>
 __global__ void __launch_bounds__(256)
 stress_kernel(const InstDesc* __restrict__ insts, const int* __restrict__ ilist) {
     LB_POINTWISE_PROLOGUE
-    const T rho = fld[RHO * nc + e], Tm = fld[TT * nc + e];
-    const T rx = fld[RX * nc + e], ry = fld[RY * nc + e], lap = fld[LAP * nc + e];
-    const T Tx = fld[TX * nc + e], Ty = fld[TY * nc + e];
-    const T uxx = fld[UXX * nc + e], uxy = fld[UXY * nc + e];   // d_x u_x, d_y u_x
-    const T uyx = fld[UYX * nc + e], uyy = fld[UYY * nc + e];   // d_x u_y, d_y u_y
-    const T gdx = fld[GDX * nc + e], gdy = fld[GDY * nc + e];
+    const T rho = fieldp<T>(I, RHO)[e], Tm = fieldp<T>(I, TT)[e];
+    const T rx = fieldp<T>(I, RX)[e], ry = fieldp<T>(I, RY)[e], lap = fieldp<T>(I, LAP)[e];
+    const T Tx = fieldp<T>(I, TX)[e], Ty = fieldp<T>(I, TY)[e];
+    const T uxx = fieldp<T>(I, UXX)[e], uxy = fieldp<T>(I, UXY)[e];   // d_x u_x, d_y u_x
+    const T uyx = fieldp<T>(I, UYX)[e], uyy = fieldp<T>(I, UYY)[e];   // d_x u_y, d_y u_y
+    const T gdx = fieldp<T>(I, GDX)[e], gdy = fieldp<T>(I, GDY)[e];
     const T K = T(I.K), H = T(I.H), zeta = T(I.zeta), a = T(I.a), bw = T(I.bw);
 
     const T div = uxx + uyy;
@@ -409,18 +465,18 @@ stress_kernel(const InstDesc* __restrict__ insts, const int* __restrict__ ilist)
     const T iso = -M * (rho * lap + T(0.5) * g2) - rT * (rx * mtx + ry * mty);
     const T Lxx = M * rx * rx + iso, Lxy = M * rx * ry, Lyy = M * ry * ry + iso;
     const T pn = Pw - rT;
-    fld[SXX * nc + e] = pn + Lxx - zeta * div;
-    fld[SXY * nc + e] = Lxy;
-    fld[SYY * nc + e] = pn + Lyy - zeta * div;
+    fieldp<T>(I, SXX)[e] = pn + Lxx - zeta * div;
+    fieldp<T>(I, SXY)[e] = Lxy;
+    fieldp<T>(I, SYY)[e] = pn + Lyy - zeta * div;
     const T lam_du = Lxx * uxx + Lxy * uyx + Lxy * uxy + Lyy * uyy;
     const T rgr = rx * (uxx * rx + uyx * ry) + ry * (uxy * rx + uyy * ry);
     const T num = pn * div + lam_du - zeta * div * div + a * rho * rho * div +
                   K * (T(-0.5) * g2 * div - rho * (rx * gdx + ry * gdy) - rgr);
-    fld[C0 * nc + e] = num / (T(2) * rT * Tm);
+    fieldp<T>(I, C0)[e] = num / (T(2) * rT * Tm);
     if (I.q != 0.0) {
         const T qrt = T(I.q) * rT;
-        fld[QX * nc + e] = qrt * Tx;
-        fld[QY * nc + e] = qrt * Ty;
+        fieldp<T>(I, QX)[e] = qrt * Tx;
+        fieldp<T>(I, QY)[e] = qrt * Ty;
     }
 }
 
@@ -431,13 +487,14 @@ __global__ void __launch_bounds__(256)
 init_kernel(const InstDesc* __restrict__ insts, const int* __restrict__ ilist,
             const DvmConst<double>* __restrict__ dvm) {
     LB_POINTWISE_PROLOGUE
-    const double* stage = reinterpret_cast<const double*>(fld + F_B * nc);
+    const int64_t nc = I.ncell;
+    const LB_GLOBAL double* stage = gcast(reinterpret_cast<const double*>(reinterpret_cast<const T*>(I.base) + F_B * nc));
     const double rho = stage[e], ux = stage[nc + e], uy = stage[2 * nc + e], Tm = stage[3 * nc + e];
     double f[16];
 #pragma unroll
     for (int i = 0; i < 16; ++i) f[i] = feq_pop<double>(*dvm, i, rho, ux, uy, Tm, I.b);
 #pragma unroll
-    for (int i = 0; i < 16; ++i) fld[(F_A + i) * nc + e] = T(f[i]);
+    for (int i = 0; i < 16; ++i) fieldp<T>(I, F_A + i)[e] = T(f[i]);
 }
 
 // Per-cell conserved densities, summed per block in float64:
@@ -447,13 +504,11 @@ template <typename T>
 __global__ void __launch_bounds__(256)
 conserve_partial(const InstDesc* __restrict__ insts, int inst) {
     const InstDesc& I = insts[inst];
-    const int64_t nc = I.ncell;
-    const T* fld = reinterpret_cast<const T*>(I.base);
+    const uint32_t nc = (uint32_t)I.ncell;
     double acc[5] = {0, 0, 0, 0, 0};
-    for (int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; e < nc;
-         e += (int64_t)gridDim.x * blockDim.x) {
-        const double rho = fld[RHO * nc + e], ux = fld[UX * nc + e], uy = fld[UY * nc + e];
-        const double Tm = fld[TT * nc + e], rx = fld[RX * nc + e], ry = fld[RY * nc + e];
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < nc; e += gridDim.x * blockDim.x) {
+        const double rho = fieldp<T>(I, RHO)[e], ux = fieldp<T>(I, UX)[e], uy = fieldp<T>(I, UY)[e];
+        const double Tm = fieldp<T>(I, TT)[e], rx = fieldp<T>(I, RX)[e], ry = fieldp<T>(I, RY)[e];
         const double en = 0.5 * rho * (I.b * Tm + ux * ux + uy * uy) - I.a * rho * rho +
                           0.5 * I.K * (rx * rx + ry * ry);
         acc[0] += rho;

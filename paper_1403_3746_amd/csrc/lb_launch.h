@@ -17,6 +17,7 @@ struct LaunchSet {
     hipStream_t stream;
     // when set, the launch timestamps its own start and end into these events
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;
+    int ppb = 1;   // populations per block of the x population pass (tuned per size class)
 };
 
 // Launch through hipExtLaunchKernelGGL when the set carries timing events.

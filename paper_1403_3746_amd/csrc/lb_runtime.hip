@@ -170,11 +170,13 @@ struct lb_ctx {
     // size classes: instances sharing (nx, ny), as a slice [start, start+count) of ilist
     struct Class {
         int nx, ny, start, count;
+        int ppb = 1;   // tuned populations per block of the x population pass
     };
     std::vector<Class> classes;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
     bool use_graph = true;
+    int ppb_override = 0;   // populations per x-pass block forced by LBFFT_PPB (1, 2 or 4), else tuned
 
     template <typename Q>
     Q* dev(size_t off) const { return reinterpret_cast<Q*>(ws + off); }
@@ -278,12 +280,17 @@ void build_jobs(lb_ctx& c) {
 }
 
 LaunchSet set_of(const lb_ctx& c, const lb_ctx::Class& k) {
-    return LaunchSet{c.d_insts(), c.d_ilist(k.start), k.count, k.nx, k.ny, c.stream};
+    LaunchSet L{c.d_insts(), c.d_ilist(k.start), k.count, k.nx, k.ny, c.stream};
+    L.ppb = k.ppb;
+    return L;
 }
 
 LaunchSet set_one(const lb_ctx& c, int inst, hipStream_t s) {
     // the second half of ilist is the identity map
-    return LaunchSet{c.d_insts(), c.d_ilist(c.n + inst), 1, c.p[inst].nx, c.p[inst].ny, s};
+    LaunchSet L{c.d_insts(), c.d_ilist(c.n + inst), 1, c.p[inst].nx, c.p[inst].ny, s};
+    for (const auto& k : c.classes)
+        if (k.nx == L.nx && k.ny == L.ny) L.ppb = k.ppb;
+    return L;
 }
 
 hipError_t macro(const lb_ctx& c, const LaunchSet& L, int dir, int j0, int nj) {
@@ -309,8 +316,9 @@ struct PassHook {
 
 hipError_t pop_x(const lb_ctx& c, const LaunchSet& L, StageArgs st) {
     const int* pops = c.dev<int>(c.lay.pops);
-    if (c.prec == LB_FP64) return pop_x_f64(L, c.dev<DvmConst<double>>(c.lay.dvm64), pops, c.npops, st);
-    return pop_x_f32(L, c.dev<DvmConst<float>>(c.lay.dvm32), pops, c.npops, st);
+    const int ppb = c.ppb_override ? c.ppb_override : L.ppb;
+    if (c.prec == LB_FP64) return pop_x_f64(L, c.dev<DvmConst<double>>(c.lay.dvm64), pops, ppb, st);
+    return pop_x_f32(L, c.dev<DvmConst<float>>(c.lay.dvm32), pops, ppb, st);
 }
 
 hipError_t pop_y(const lb_ctx& c, const LaunchSet& L, StageArgs st) {
@@ -350,28 +358,89 @@ hipError_t pop_passes(const lb_ctx& c, const LaunchSet& L, StageArgs st) {
     return pop_y(c, L, st);
 }
 
-// One Runge-Kutta stage of every instance on stream s: each pass kind is launched for every
-// size class before the next pass kind.
-hipError_t enqueue_stage(const lb_ctx& c, hipStream_t s, StageArgs st, PassHook* hook = nullptr) {
+// One Runge-Kutta stage of the instances of one size class on stream s.
+hipError_t enqueue_class_stage(const lb_ctx& c, const lb_ctx::Class& cl, hipStream_t s,
+                               StageArgs st, PassHook* hook) {
     for (int k = 0; k < LB_NPASS; ++k) {
-        for (const auto& cl : c.classes) {
-            LaunchSet L = set_of(c, cl);
-            L.stream = s;
-            if (hook && !hook->events(k, &L.ev_start, &L.ev_stop)) return hipErrorInvalidValue;
-            hipError_t e = run_pass(c, L, k, st);
-            if (e != hipSuccess) return e;
-        }
+        LaunchSet L = set_of(c, cl);
+        L.stream = s;
+        if (hook && !hook->events(k, &L.ev_start, &L.ev_stop)) return hipErrorInvalidValue;
+        hipError_t e = run_pass(c, L, k, st);
+        if (e != hipSuccess) return e;
     }
     return hipSuccess;
 }
 
-// f^{n+1/2} = f^n + dt/2 R(f^n) into F_B;  f^{n+1} = f^n + dt R(f^{n+1/2}) into F_A.
-hipError_t enqueue_step(const lb_ctx& c, hipStream_t s, PassHook* hook = nullptr) {
+// f^{n+1/2} = f^n + dt/2 R(f^n) into F_B;  f^{n+1} = f^n + dt R(f^{n+1/2}) into F_A, for one
+// size class.
+hipError_t enqueue_class_step(const lb_ctx& c, const lb_ctx::Class& cl, hipStream_t s,
+                              PassHook* hook = nullptr) {
     StageArgs s1{F_A, F_A, F_B, 0.5, 1};
     StageArgs s2{F_B, F_A, F_A, 1.0, 1};
-    hipError_t e = enqueue_stage(c, s, s1, hook);
+    hipError_t e = enqueue_class_stage(c, cl, s, s1, hook);
     if (e != hipSuccess) return e;
-    return enqueue_stage(c, s, s2, hook);
+    return enqueue_class_stage(c, cl, s, s2, hook);
+}
+
+// One step of every instance on stream s, size classes one after the other.
+hipError_t enqueue_step(const lb_ctx& c, hipStream_t s, PassHook* hook = nullptr) {
+    for (const auto& cl : c.classes) {
+        hipError_t e = enqueue_class_step(c, cl, s, hook);
+        if (e != hipSuccess) return e;
+    }
+    return hipSuccess;
+}
+
+// One step captured with the size classes as parallel branches: the capture stream forks to one
+// stream per class (default priority) and joins them again.
+hipError_t capture_step(const lb_ctx& c, hipStream_t cs, std::vector<hipStream_t>& br,
+                        std::vector<hipEvent_t>& ev) {
+    if (c.classes.size() <= 1) return enqueue_step(c, cs);
+    hipError_t e = hipEventRecord(ev[0], cs);
+    for (size_t k = 0; e == hipSuccess && k < c.classes.size(); ++k) {
+        e = hipStreamWaitEvent(br[k], ev[0], 0);
+        if (e == hipSuccess) e = enqueue_class_step(c, c.classes[k], br[k]);
+        if (e == hipSuccess) e = hipEventRecord(ev[k + 1], br[k]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(cs, ev[k + 1], 0);
+    }
+    return e;
+}
+
+// Populations per block of the x population pass: time 1, 2 and 4 on the class's own data
+// (stage-1 arguments, which leave the state untouched) and keep the fastest.
+hipError_t tune_class(lb_ctx& c, lb_ctx::Class& cl) {
+    LaunchSet L = set_of(c, cl);
+    hipError_t e = force_passes(c, L, F_A);
+    if (e != hipSuccess) return e;
+    const StageArgs st{F_A, F_A, F_B, 0.5, 1};
+    hipEvent_t a, b;
+    if ((e = hipEventCreate(&a)) != hipSuccess) return e;
+    if ((e = hipEventCreate(&b)) != hipSuccess) return e;
+    float best = 1e30f;
+    for (int ppb : {1, 2, 4}) {
+        L.ppb = ppb;
+        float ms = 0.f;
+        for (int it = 0; it < 4 && e == hipSuccess; ++it) {
+            e = hipEventRecord(a, c.stream);
+            if (e == hipSuccess) e = pop_x(c, L, st);
+            if (e == hipSuccess) e = hipEventRecord(b, c.stream);
+            if (e == hipSuccess) e = hipEventSynchronize(b);
+            float t = 0.f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+            if (it > 0) ms += t;   // the first launch warms caches
+        }
+        if (e != hipSuccess) break;
+        if (std::getenv("LBFFT_VERBOSE"))
+            std::fprintf(stderr, "lbfft tune: class %dx%d x%d  pops/block %d  %.4f ms\n", cl.nx, cl.ny,
+                         cl.count, ppb, ms / 3.0);
+        if (ms < best) {
+            best = ms;
+            cl.ppb = ppb;
+        }
+    }
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return e;
 }
 
 lb_status check_inst(const lb_ctx* c, int inst) {
@@ -479,6 +548,10 @@ lb_status lb_init(lb_ctx** out, int n_inst, const lb_params* p, const lb_dvm* dv
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
     c->lay = lay;
     if (const char* g = std::getenv("LBFFT_NO_GRAPH")) c->use_graph = !(g[0] == '1');
+    if (const char* g = std::getenv("LBFFT_PPB")) {
+        const int v = std::atoi(g);
+        if (v == 1 || v == 2 || v == 4) c->ppb_override = v;
+    }
 
     if (!build_dvm(c->dvm, c->dvm64)) {
         delete c;
@@ -492,6 +565,15 @@ lb_status lb_init(lb_ctx** out, int n_inst, const lb_params* p, const lb_dvm* dv
     }
     for (int i = 0; i < 16; ++i)
         if (c->dvm64.vy[i] != 0.0) c->pops_h[c->npops++] = i;
+    // x-pass order: populations with v_x != 0 in pairs of the same ring, then the v_x = 0 ones
+    {
+        int k = 0;
+        for (int i = 0; i < 16; ++i)
+            if (c->dvm64.vx[i] != 0.0) c->dvm64.xorder[k++] = i;
+        for (int i = 0; i < 16; ++i)
+            if (c->dvm64.vx[i] == 0.0) c->dvm64.xorder[k++] = i;
+        for (int i = 0; i < 16; ++i) c->dvm32.xorder[i] = c->dvm64.xorder[i];
+    }
     build_jobs(*c);
 
     // instance descriptors and size classes
@@ -593,20 +675,45 @@ lb_status lb_init(lb_ctx** out, int n_inst, const lb_params* p, const lb_dvm* dv
             st = fail(LB_E_HIP, "init sync: %s", hipGetErrorString(e));
         }
     }
-    // capture one Runge-Kutta step into a graph (on a private stream of default priority)
+    // tune the launch variants of each size class on its own data (unless disabled)
+    const char* tune_env = std::getenv("LBFFT_TUNE");
+    const bool tune = !(tune_env && tune_env[0] == '0');
+    for (auto& cl : c->classes) {
+        if (!ok) break;
+        const int64_t cells = (int64_t)cl.nx * cl.ny * cl.count;
+        cl.ppb = cells >= (1 << 20) ? 2 : 1;   // default without tuning
+        if (tune && !c->ppb_override) {
+            hipError_t e = tune_class(*c, cl);
+            if (e != hipSuccess) {
+                ok = false;
+                st = fail(LB_E_HIP, "tuning: %s", hipGetErrorString(e));
+            }
+        }
+    }
+    // capture one Runge-Kutta step into a graph: private streams of default priority, one
+    // branch per size class
     if (ok && c->use_graph) {
-        hipStream_t cs;
+        const size_t nb = c->classes.size();
+        std::vector<hipStream_t> br(nb, nullptr);
+        std::vector<hipEvent_t> ev(nb + 1, nullptr);
+        hipStream_t cs = nullptr;
         hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+        for (size_t k = 0; e == hipSuccess && k < nb; ++k) e = hipStreamCreateWithFlags(&br[k], hipStreamNonBlocking);
+        for (size_t k = 0; e == hipSuccess && k <= nb; ++k) e = hipEventCreateWithFlags(&ev[k], hipEventDisableTiming);
         if (e == hipSuccess) {
             e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
             if (e == hipSuccess) {
-                hipError_t e2 = enqueue_step(*c, cs);
+                hipError_t e2 = capture_step(*c, cs, br, ev);
                 e = hipStreamEndCapture(cs, &c->graph);
                 if (e2 != hipSuccess) e = e2;
             }
             if (e == hipSuccess) e = hipGraphInstantiate(&c->exec, c->graph, nullptr, nullptr, 0);
-            (void)hipStreamDestroy(cs);
         }
+        for (auto x : ev)
+            if (x) (void)hipEventDestroy(x);
+        for (auto x : br)
+            if (x) (void)hipStreamDestroy(x);
+        if (cs) (void)hipStreamDestroy(cs);
         if (e != hipSuccess) {
             ok = false;
             st = fail(LB_E_HIP, "graph capture: %s", hipGetErrorString(e));
@@ -772,6 +879,16 @@ lb_status lb_derivative(lb_ctx* c, int inst, int axis, int order, const double* 
     const int j = axis == 0 ? (order == 1 ? c->j_dx : c->j_dxx) : (order == 1 ? c->j_dy : c->j_dyy);
     LB_HIP(macro(*c, set_one(*c, inst, c->stream), axis, j, 1));
     return field_to_host(c, inst, SCR1, out);
+}
+
+lb_status lb_plan_info(lb_ctx* c, int inst, int* out, int n) {
+    lb_status s = check_inst(c, inst);
+    if (s != LB_OK) return s;
+    if (!out || n < 2) return fail(LB_E_ARG, "need an output array of length >= 2");
+    out[0] = set_one(*c, inst, c->stream).ppb;
+    if (c->ppb_override) out[0] = c->ppb_override;
+    out[1] = (int)c->classes.size();
+    return LB_OK;
 }
 
 void lb_free(lb_ctx* c) {

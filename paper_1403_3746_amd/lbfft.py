@@ -20,7 +20,7 @@ _STATUS = {0: "LB_OK", -1: "LB_E_ARG", -2: "LB_E_SIZE", -3: "LB_E_NOMEM", -4: "L
 
 EXPORTS = ("lb_workspace_bytes", "lb_init", "lb_step", "lb_sync", "lb_moments", "lb_conservation",
            "lb_get_f", "lb_set_f", "lb_force_coefficients", "lb_rhs", "lb_derivative",
-           "lb_step_timed", "lb_free", "lb_last_error")
+           "lb_step_timed", "lb_plan_info", "lb_free", "lb_last_error")
 PASS_NAMES = ("moments", "macro_x1", "macro_y1", "stress", "macro_x2", "macro_y2", "pop_x", "pop_y")
 
 
@@ -70,6 +70,7 @@ def load():
     lib.lb_rhs.argtypes = [V, I, dp]
     lib.lb_derivative.argtypes = [V, I, I, I, dp, dp]
     lib.lb_step_timed.argtypes = [V, I, dp]
+    lib.lb_plan_info.argtypes = [V, I, ctypes.POINTER(ctypes.c_int), I]
     lib.lb_free.argtypes = [V]
     lib.lb_free.restype = None
     lib.lb_last_error.restype = ctypes.c_char_p
@@ -189,6 +190,12 @@ def lb_step_timed(ctx, n_steps):
     return dict(zip(PASS_NAMES, ms.tolist()))
 
 
+def lb_plan_info(ctx, inst):
+    out = (ctypes.c_int * 2)()
+    _check(load().lb_plan_info(ctx, inst, out, 2))
+    return dict(pops_per_block_x=out[0], size_classes=out[1])
+
+
 def lb_free(ctx):
     if ctx:
         load().lb_free(ctx)
@@ -247,6 +254,9 @@ class Sim:
 
     def step_timed(self, n):
         return lb_step_timed(self.ctx, n)
+
+    def plan(self, inst=0):
+        return lb_plan_info(self.ctx, inst)
 
     def close(self):
         if getattr(self, "ctx", None):

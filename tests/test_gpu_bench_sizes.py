@@ -1,0 +1,136 @@
+"""GPU parity at the benchmark sizes, in the launch configuration the benchmark times.
+
+Where the oracle is too slow to run inside a test (512^2 for 100 steps, the ragged batch with
+grids up to 1024^2 for 50 steps), the HIP results are compared with oracle samples written by
+tests/golden/make_oracle_samples.py (oracle only: moments at a fixed random sample of cells plus
+each field's max |value| over the grid, the denominators of the parity norm)."""
+import os
+
+import numpy as np
+import pytest
+
+from oracle import model, spectral
+from paper_1403_3746_amd import workloads as W
+from tests.gpu_util import field_errors, say
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def torch_cuda():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    return torch
+
+
+def _sim(instances, precision):
+    from paper_1403_3746_amd.lbfft import Sim
+    return Sim(instances, precision)
+
+
+def _samples(name):
+    path = os.path.join(GOLDEN, f"{name}_oracle.npz")
+    if not os.path.exists(path):
+        pytest.skip(f"{path} not generated")
+    return np.load(path)
+
+
+def _sample_errors(mom_gpu, z, key, step):
+    """Parity norm on sampled cells: rho, T relative to the oracle field's max |value|, u relative
+    to sqrt(max T)."""
+    idx = z[f"{key}_idx"]
+    g = {n: a.reshape(-1)[idx] for n, a in zip(("rho", "ux", "uy", "T"), mom_gpu)}
+    e = {}
+    for n in ("rho", "T"):
+        ref = z[f"{key}_s{step}_{n}"]
+        e[n] = float(np.abs(g[n] - ref).max() / z[f"{key}_s{step}_{n}_absmax"])
+    sT = np.sqrt(float(z[f"{key}_s{step}_T_absmax"]))
+    e["u"] = float(max(np.abs(g["ux"] - z[f"{key}_s{step}_ux"]).max(),
+                       np.abs(g["uy"] - z[f"{key}_s{step}_uy"]).max()) / sT)
+    return e
+
+
+def test_quench512_fp64_first_steps_live(torch_cuda):
+    (p, ic), = W.config("quench512")[0]
+    spectral.set_workers(os.cpu_count() or 1)
+    sim = _sim([(p, ic)], "fp64")
+    f_ref = model.init_equilibrium(*ic, p)
+    for n in range(1, 4):
+        sim.step(1)
+        f_ref = model.rk2_step(f_ref, p)
+        errs = field_errors(sim.get_f(), f_ref, lambda f: model.moments(f, p))
+        say(f"quench512 fp64 step {n}: {errs}")
+        assert max(errs.values()) < 1e-12
+    spectral.set_workers(1)
+    sim.close()
+
+
+@pytest.mark.parametrize("prec,tol", [("fp64", 1e-12), ("fp32", 1e-5)])
+def test_quench512_steps_10_and_100_vs_oracle_samples(torch_cuda, prec, tol):
+    z = _samples("quench512")
+    (p, ic), = W.config("quench512")[0]
+    sim = _sim([(p, ic)], prec)
+    sim.step(10)
+    e10 = _sample_errors(sim.moments(), z, "i0", 10)
+    sim.step(90)
+    e100 = _sample_errors(sim.moments(), z, "i0", 100)
+    say(f"quench512 {prec}: step 10 {e10}  step 100 {e100}")
+    if prec == "fp64":
+        assert max(e10.values()) < tol and max(e100.values()) < tol
+    else:
+        assert e100["rho"] < tol and e100["T"] < tol
+    sim.close()
+
+
+def test_batch128x256_fp32_step50(torch_cuda):
+    insts, _ = W.config("batch128x256")
+    sim = _sim(insts, "fp32")
+    say(f"batch plan: {sim.plan(0)}")
+    sim.step(50)
+    for k in (0, 127, 255):
+        p, ic = insts[k]
+        f_ref = model.run(model.init_equilibrium(*ic, p), p, 50)
+        errs = field_errors(sim.get_f(k), f_ref, lambda f: model.moments(f, p))
+        say(f"batch inst {k} fp32 step 50 vs oracle: {errs}")
+        assert errs["rho"] < 1e-5 and errs["T"] < 1e-5
+        solo = _sim([(p, ic)], "fp32")
+        solo.step(50)
+        d = float(np.abs(solo.get_f() - sim.get_f(k)).max() / np.abs(f_ref).max())
+        say(f"batch inst {k} vs solo run: {d:.2e}")
+        assert d < 1e-6
+        solo.close()
+    sim.close()
+
+
+def test_ragged64_fp32_every_instance_step50(torch_cuda):
+    z = _samples("ragged64")
+    insts, _ = W.config("ragged64")
+    sim = _sim(insts, "fp32")
+    sim.step(50)
+    worst = 0.0
+    for k, (p, ic) in enumerate(insts):
+        e = _sample_errors(sim.moments(k), z, f"i{k}", 50)
+        worst = max(worst, e["rho"], e["T"])
+        assert e["rho"] < 1e-5 and e["T"] < 1e-5, (k, ic[0].shape, e)
+    say(f"ragged64 fp32 step 50: worst rho/T error over 64 instances {worst:.2e}")
+    sim.close()
+
+
+def test_quench2048_fp32_conservation(torch_cuda):
+    (p, ic), = W.config("quench2048")[0]
+    spectral.set_workers(os.cpu_count() or 1)
+    ref = model.conservation(model.init_equilibrium(*ic, p), p)
+    spectral.set_workers(1)
+    sim = _sim([(p, ic)], "fp32")
+    c0 = sim.conservation()
+    say(f"quench2048 conservation at start: gpu {c0} oracle {ref}")
+    assert abs(c0[0] - ref[0]) < 1e-6 * abs(ref[0])
+    assert abs(c0[3] - ref[3]) < 1e-5 * abs(ref[3])
+    sim.step(100)
+    c1 = sim.conservation()
+    drift = (c1 - c0) / abs(c0[0])
+    say(f"quench2048 fp32 drift after 100 steps (relative to mass): {drift}")
+    assert abs(drift[0]) < 1e-6 and abs(drift[1]) < 1e-6 and abs(drift[2]) < 1e-6
+    sim.close()
