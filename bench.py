@@ -151,7 +151,8 @@ def main():
     ap.add_argument("--timed-steps", type=int, default=50)
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--only", choices=("quench512_fp64", "quench512_fp32", "batch128x256_fp32"),
+    ap.add_argument("--only", choices=("quench512_fp64", "quench512_fp32", "batch128x256_fp32",
+                                       "ragged64_fp32", "quench2048_fp32", "slab64_fp64"),
                     help="run one workload only and print its summary (for profiling)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="finish with a 256 MiB device-to-device copy (HBM counter calibration)")

@@ -66,6 +66,8 @@ typedef struct {
     double q;         /* heat-flux coefficient of C_q                                          */
     double b_dof;     /* total degrees of freedom b (> 0)                                      */
     double vdw_a, vdw_b; /* van der Waals a and b_w                                            */
+    int32_t hist_len; /* steps of per-step float64 conservation history kept (ring buffer);
+                         0 = none.  See lb_conservation_history.                                */
 } lb_params;
 
 /* D2V16 ring speeds (Sec. 2.1; the paper defers the values to Kataoka and Tsutahara).  Axis
@@ -112,6 +114,16 @@ lb_status lb_moments(lb_ctx* ctx, int inst, double* rho, double* ux, double* uy,
  * K |grad rho|^2/2 (Sec. 2.2; rho T - a rho^2 + K|grad rho|^2/2 + rho u^2/2 at b = 2), gradients
  * by the windowed FFT.  Synchronises.  Returns LB_E_NONFINITE if the state holds NaN/Inf. */
 lb_status lb_conservation(lb_ctx* ctx, int inst, double out[4]);
+
+/* Per-step conservation history (instances with hist_len > 0).  Every lb_step records, on the
+ * GPU inside the captured step and in float64 in both precisions, the four integrals of
+ * lb_conservation for the state at the start of the step (step index 0, 1, 2, ...; the first
+ * stage's moments and d_x rho, d_y rho are reused, so nothing is recomputed).  This copies the
+ * latest min(recorded, hist_len, max_entries) entries, oldest first, into out[n][4], sets *n_out
+ * and *first_step (step index of out[0]).  Synchronises.  LB_E_STATE if hist_len = 0,
+ * LB_E_NONFINITE if an entry is NaN/Inf. */
+lb_status lb_conservation_history(lb_ctx* ctx, int inst, int max_entries, double* out, int* n_out,
+                                  long long* first_step);
 
 /* Copy the populations of instance inst to / from a host float64 array [16][ny][nx]
  * (checkpoint and restart; in FP32 mode lb_set_f rounds to float32).  Synchronise. */

@@ -21,6 +21,9 @@
 #ifndef LB_EPI_GROUP
 #define LB_EPI_GROUP 4   // epilogue positions whose field loads may be hoisted together
 #endif
+#ifndef LB_YSEG
+#define LB_YSEG 128      // bytes of each row a y-pass tile covers (2 * lines per block * word)
+#endif
 #ifndef LB_POPX_WAVES
 #define LB_POPX_WAVES 4  // waves per SIMD the single-population x pass must fit (register budget)
 #endif
@@ -41,9 +44,9 @@ struct LineCfg {
     static constexpr int at_least(int l, int lo) { return l < lo ? lo : l; }
     // x: one line per block unless lines are short (then fill one wave)
     static constexpr int lpw_x() { return at_least(64 / TPL, 1); }
-    // y: 32-byte row segments, at least one wave per block, at most 512 threads
+    // y: LB_YSEG-byte row segments, at least one wave per block, at most 512 threads
     static constexpr int lpw_y() {
-        int l = at_least(at_least(32 / CB, 64 / TPL), 1);
+        int l = at_least(at_least(LB_YSEG / CB, 64 / TPL), 1);
         return (l * TPL > 512) ? at_least(512 / TPL, 1) : l;
     }
     static constexpr int LPW = DIR == 0 ? lpw_x() : lpw_y();
@@ -259,6 +262,27 @@ __device__ __forceinline__ T feq_dot(const DvmConst<T>& D, int i, T rho, const T
     return rho * s;
 }
 
+// Equilibria of a mirror pair (i0, i1): i1 is i0 reflected in x (AX = 0) or y (AX = 1), so row i1
+// of C^{-1} is row i0 with the sign of the moments odd in v_x (resp. v_y) flipped.  With E, O the
+// even and odd parts of row i0's dot product, f^eq_i0 = rho (E + O) and f^eq_i1 = rho (E - O).
+// Odd moments in the row order of meq_unit: v_x -> 1, 5, 7, 9, 11, 14; v_y -> 2, 5, 8, 10, 12, 14.
+template <typename T, int AX>
+__device__ __forceinline__ void feq_mirror_pair(const DvmConst<T>& D, int i0, T rho,
+                                                const T (&m)[16], T& fe0, T& fe1) {
+    constexpr unsigned ODD = AX == 0 ? ((1u << 1) | (1u << 5) | (1u << 7) | (1u << 9) | (1u << 11) | (1u << 14))
+                                     : ((1u << 2) | (1u << 5) | (1u << 8) | (1u << 10) | (1u << 12) | (1u << 14));
+    T e = T(0), o = T(0);
+#pragma unroll
+    for (int j = 0; j < 16; ++j) {
+        if ((ODD >> j) & 1u)
+            o += D.cinv[i0][j] * m[j];
+        else
+            e += D.cinv[i0][j] * m[j];
+    }
+    fe0 = rho * (e + o);
+    fe1 = rho * (e - o);
+}
+
 template <typename T>
 __device__ __forceinline__ T feq_pop(const DvmConst<T>& D, int i, T rho, T ux, T uy, T Tm, T b) {
     T m[16];
@@ -344,18 +368,31 @@ pop_x_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
             meq_unit(ux, uy, Tm, b, mq);
             // I_i = -[A + B.(v_i - u) + D |v_i - u|^2] f^eq_i with A = -2 D T
             const T g0 = T(-2) * Dc * Tm;
+            T fe[P];
+            if constexpr (P == 1) {
+                fe[0] = feq_dot(D, D.xorder[w.job], rho, mq);
+            } else {
+#pragma unroll
+                for (int q = 0; q < P; q += 2) {
+                    const int i0 = D.xorder[w.job * P + q];
+                    // pairs of populations with v_x != 0 are x mirrors, the others y mirrors
+                    if (D.vx[i0] != T(0))
+                        feq_mirror_pair<T, 0>(D, i0, rho, mq, fe[q], fe[q + 1]);
+                    else
+                        feq_mirror_pair<T, 1>(D, i0, rho, mq, fe[q], fe[q + 1]);
+                }
+            }
 #pragma unroll
             for (int q = 0; q < P; ++q) {
                 const int i = D.xorder[w.job * P + q];
                 const T vx = D.vx[i], vy = D.vy[i];
-                const T fe = feq_dot(D, i, rho, mq);
                 const T cx = vx - ux, cy = vy - uy;
-                const T force = -(g0 + Bx * cx + By * cy + Dc * (cx * cx + cy * cy)) * fe;
+                const T force = -(g0 + Bx * cx + By * cy + Dc * (cx * cx + cy * cy)) * fe[q];
                 const T lin = h == 0 ? X[q][m].re : X[q][m].im;
                 const T base = has_base ? fieldp<T>(I, st.base_field + i)[e] : T(0);
                 // out may equal the base block (second stage writes f^{n+1} over f^n per cell)
                 LB_GLOBAL T* out = fieldp<T>(I, (vy == T(0) ? st.out_field : F_P) + i);
-                out[e] = base + lin + c * (force + fe * inv_tau);
+                out[e] = base + lin + c * (force + fe[q] * inv_tau);
             }
         }
     }
@@ -497,18 +534,23 @@ init_kernel(const InstDesc* __restrict__ insts, const int* __restrict__ ilist,
     for (int i = 0; i < 16; ++i) fieldp<T>(I, F_A + i)[e] = T(f[i]);
 }
 
-// Per-cell conserved densities, summed per block in float64:
-//   mass rho, momentum rho u, energy rho (b T + u^2)/2 - a rho^2 + K |grad rho|^2 / 2.
-// Block partial sums are written to red[blockIdx.x * 5 + k]; k = 4 counts non-finite cells.
+// Per-cell conserved densities, summed per block in float64 (grid: red_blocks x instances):
+//   mass rho, momentum rho u, energy rho (b T + u^2)/2 - a rho^2 + K |grad rho|^2 / 2 (Sec. 2.2),
+// and a count of non-finite cells.  Block partials go to I.red[block * 5 + k].
 template <typename T>
 __global__ void __launch_bounds__(256)
-conserve_partial(const InstDesc* __restrict__ insts, int inst) {
-    const InstDesc& I = insts[inst];
+conserve_partial(const InstDesc* __restrict__ insts, const int* __restrict__ ilist) {
+    const InstDesc& I = insts[ilist[blockIdx.y]];
     const uint32_t nc = (uint32_t)I.ncell;
     double acc[5] = {0, 0, 0, 0, 0};
-    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < nc; e += gridDim.x * blockDim.x) {
-        const double rho = fieldp<T>(I, RHO)[e], ux = fieldp<T>(I, UX)[e], uy = fieldp<T>(I, UY)[e];
-        const double Tm = fieldp<T>(I, TT)[e], rx = fieldp<T>(I, RX)[e], ry = fieldp<T>(I, RY)[e];
+    const LB_GLOBAL T* rp = fieldp<T>(I, RHO);
+    const LB_GLOBAL T* xp = fieldp<T>(I, UX);
+    const LB_GLOBAL T* yp = fieldp<T>(I, UY);
+    const LB_GLOBAL T* tp = fieldp<T>(I, TT);
+    const LB_GLOBAL T* gxp = fieldp<T>(I, RX);
+    const LB_GLOBAL T* gyp = fieldp<T>(I, RY);
+    for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < nc; e += I.red_blocks * blockDim.x) {
+        const double rho = rp[e], ux = xp[e], uy = yp[e], Tm = tp[e], rx = gxp[e], ry = gyp[e];
         const double en = 0.5 * rho * (I.b * Tm + ux * ux + uy * uy) - I.a * rho * rho +
                           0.5 * I.K * (rx * rx + ry * ry);
         acc[0] += rho;
@@ -528,10 +570,7 @@ conserve_partial(const InstDesc* __restrict__ insts, int inst) {
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int k = 0; k < 5; ++k) I.red[blockIdx.x * 5 + k] = sh[k][0];
-    }
+    if (threadIdx.x < 5) I.red[blockIdx.x * 5 + threadIdx.x] = sh[threadIdx.x][0];
 }
 
 // Convert between the working precision and float64 (host transfers of non-hot calls).

@@ -49,8 +49,9 @@ template <typename T>
 hipError_t launch_init(const LaunchSet& L, const DvmConst<double>* dvm);
 template <typename T>
 hipError_t launch_tables(const InstDesc* insts, int inst, int nx, int ny, hipStream_t s);
+// Conservation sums of the instances of L (needs moments and d_x rho, d_y rho of the state).
 template <typename T>
-hipError_t launch_conserve(const InstDesc* insts, int inst, int nblocks, hipStream_t s);
+hipError_t launch_conserve(const LaunchSet& L, int record);
 template <typename T>
 hipError_t launch_to_f64(const void* src, double* dst, int64_t n, hipStream_t s);
 template <typename T>

@@ -43,6 +43,27 @@ tables_kernel(const InstDesc* __restrict__ insts, int inst) {
     }
 }
 
+// Final sum of the block partials in a fixed order (one block per instance, one thread per
+// quantity): cons = sums times dx^2 (the non-finite count unscaled); with record != 0 the four
+// integrals are also appended to the history ring buffer.
+__global__ void __launch_bounds__(64)
+conserve_final(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, int record) {
+    const InstDesc& I = insts[ilist[blockIdx.x]];
+    const int k = threadIdx.x;
+    double s = 0.0;
+    if (k < 5)
+        for (int b = 0; b < I.red_blocks; ++b) s += I.red[b * 5 + k];
+    const double area = I.dx * I.dx;
+    if (k < 5) I.cons[k] = k < 4 ? s * area : s;
+    if (record && I.hist_len > 0) {
+        __syncthreads();
+        const unsigned long long n = *I.hist_count;
+        if (k < 4) I.hist[(n % (unsigned long long)I.hist_len) * 4 + k] = s * area;
+        __syncthreads();
+        if (k == 0) *I.hist_count = n + 1;
+    }
+}
+
 }  // namespace
 
 template <typename T>
@@ -76,8 +97,12 @@ hipError_t launch_tables(const InstDesc* insts, int inst, int nx, int ny, hipStr
 }
 
 template <typename T>
-hipError_t launch_conserve(const InstDesc* insts, int inst, int nblocks, hipStream_t s) {
-    hipLaunchKernelGGL((conserve_partial<T>), dim3(nblocks), dim3(256), 0, s, insts, inst);
+hipError_t launch_conserve(const LaunchSet& L, int record) {
+    hipLaunchKernelGGL((conserve_partial<T>), dim3(RED_BLOCKS, L.ninst), dim3(256), 0, L.stream,
+                       L.insts, L.ilist);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL(conserve_final, dim3(L.ninst), dim3(64), 0, L.stream, L.insts, L.ilist, record);
     return hipGetLastError();
 }
 
@@ -100,7 +125,7 @@ hipError_t launch_from_f64(const double* src, void* dst, int64_t n, hipStream_t 
     template hipError_t launch_stress<T>(const LaunchSet&);                                \
     template hipError_t launch_init<T>(const LaunchSet&, const DvmConst<double>*);         \
     template hipError_t launch_tables<T>(const InstDesc*, int, int, int, hipStream_t);     \
-    template hipError_t launch_conserve<T>(const InstDesc*, int, int, hipStream_t);        \
+    template hipError_t launch_conserve<T>(const LaunchSet&, int);                         \
     template hipError_t launch_to_f64<T>(const void*, double*, int64_t, hipStream_t);      \
     template hipError_t launch_from_f64<T>(const double*, void*, int64_t, hipStream_t);
 LB_INST(double)

@@ -55,15 +55,12 @@ bool grid_ok(int nx, int ny) { return line_ok(nx) && (line_ok(ny) || ny == 1 || 
 
 size_t word_bytes(lb_precision p) { return p == LB_FP64 ? 8 : 4; }
 
-// Conservation partial sums: at most this many blocks, 5 doubles each.
-constexpr int RED_BLOCKS = 1024;
-
 // Workspace layout.  Header: InstDesc[n], DvmConst<double>, DvmConst<float>, job tables,
 // population list, instance index lists, reduction partials.  Then per instance: tables
 // (kx, ky, twx, twy) and the field arena.
 struct Layout {
-    size_t insts, dvm64, dvm32, jobs, pops, ilist, red, header;
-    std::vector<size_t> tables, arena;
+    size_t insts, dvm64, dvm32, jobs, pops, ilist, header;
+    std::vector<size_t> tables, red, arena;
     size_t total;
 };
 
@@ -78,13 +75,15 @@ Layout make_layout(int n, const lb_params* p, lb_precision prec) {
     L.jobs = off;  off = align_up(off + sizeof(JobDesc) * MAX_JOBS);
     L.pops = off;  off = align_up(off + sizeof(int) * 16);
     L.ilist = off; off = align_up(off + sizeof(int) * 2 * n);
-    L.red = off;   off = align_up(off + sizeof(double) * 5 * RED_BLOCKS);
     L.header = off;
     const size_t w = word_bytes(prec);
     for (int k = 0; k < n; ++k) {
         const size_t nc = (size_t)p[k].nx * p[k].ny;
         L.tables.push_back(off);
         off = align_up(off + w * (p[k].nx + p[k].ny) + 2 * w * (p[k].nx + p[k].ny) + 4 * ALIGN);
+        // conservation: partials, last result (8 doubles), history counter, history ring
+        L.red.push_back(off);
+        off = align_up(off + sizeof(double) * (5 * RED_BLOCKS + 8 + 1 + 4 * (size_t)p[k].hist_len));
         L.arena.push_back(off);
         off = align_up(off + w * nc * NFIELDS);
     }
@@ -171,6 +170,7 @@ struct lb_ctx {
     struct Class {
         int nx, ny, start, count;
         int ppb = 1;   // tuned populations per block of the x population pass
+        bool hist = false;   // some instance keeps a per-step conservation history
     };
     std::vector<Class> classes;
     hipGraph_t graph = nullptr;
@@ -367,6 +367,13 @@ hipError_t enqueue_class_stage(const lb_ctx& c, const lb_ctx::Class& cl, hipStre
         if (hook && !hook->events(k, &L.ev_start, &L.ev_stop)) return hipErrorInvalidValue;
         hipError_t e = run_pass(c, L, k, st);
         if (e != hipSuccess) return e;
+        // per-step FP64 conservation of the state f^n: its moments and d_x rho, d_y rho exist
+        // after the first stage's y derivative pass
+        if (k == LB_PASS_MACRO_Y1 && cl.hist && st.f_field == F_A && st.use_dt) {
+            L.ev_start = L.ev_stop = nullptr;
+            e = c.prec == LB_FP64 ? launch_conserve<double>(L, 1) : launch_conserve<float>(L, 1);
+            if (e != hipSuccess) return e;
+        }
     }
     return hipSuccess;
 }
@@ -492,6 +499,8 @@ lb_status validate_params(const lb_params& q, int k) {
     for (double x : v)
         if (!std::isfinite(x)) return fail(LB_E_ARG, "instance %d: non-finite parameter", k);
     if (q.vdw_b < 0) return fail(LB_E_ARG, "instance %d: vdw_b must be >= 0", k);
+    if (q.hist_len < 0 || q.hist_len > (1 << 24))
+        return fail(LB_E_ARG, "instance %d: hist_len must be in [0, 2^24]", k);
     return LB_OK;
 }
 
@@ -565,13 +574,29 @@ lb_status lb_init(lb_ctx** out, int n_inst, const lb_params* p, const lb_dvm* dv
     }
     for (int i = 0; i < 16; ++i)
         if (c->dvm64.vy[i] != 0.0) c->pops_h[c->npops++] = i;
-    // x-pass order: populations with v_x != 0 in pairs of the same ring, then the v_x = 0 ones
+    // x-pass order: mirror pairs -- populations with v_x != 0 paired with their x mirror, then the
+    // v_x = 0 ones paired with their y mirror (the kernel forms both equilibria of a pair from one
+    // split dot product).  Every ring of the D2V16 set is closed under both mirrors.
     {
         int k = 0;
-        for (int i = 0; i < 16; ++i)
-            if (c->dvm64.vx[i] != 0.0) c->dvm64.xorder[k++] = i;
-        for (int i = 0; i < 16; ++i)
-            if (c->dvm64.vx[i] == 0.0) c->dvm64.xorder[k++] = i;
+        bool used[16] = {false};
+        for (int pass = 0; pass < 2; ++pass)
+            for (int i = 0; i < 16; ++i) {
+                if (used[i] || ((c->dvm64.vx[i] != 0.0) != (pass == 0))) continue;
+                int j = -1;
+                for (int m = 0; m < 16; ++m) {
+                    const bool xm = c->dvm64.vx[m] == -c->dvm64.vx[i] && c->dvm64.vy[m] == c->dvm64.vy[i];
+                    const bool ym = c->dvm64.vx[m] == c->dvm64.vx[i] && c->dvm64.vy[m] == -c->dvm64.vy[i];
+                    if (m != i && !used[m] && (pass == 0 ? xm : ym)) j = m;
+                }
+                if (j < 0) {
+                    delete c;
+                    return fail(LB_E_ARG, "velocity set is not closed under mirror reflections");
+                }
+                used[i] = used[j] = true;
+                c->dvm64.xorder[k++] = i;
+                c->dvm64.xorder[k++] = j;
+            }
         for (int i = 0; i < 16; ++i) c->dvm32.xorder[i] = c->dvm64.xorder[i];
     }
     build_jobs(*c);
@@ -591,7 +616,13 @@ lb_status lb_init(lb_ctx** out, int n_inst, const lb_params* p, const lb_dvm* dv
         I.ky = c->ws + t;  t = align_up(t + w * I.ny);
         I.twx = c->ws + t; t = align_up(t + 2 * w * I.nx);
         I.twy = c->ws + t;
-        I.red = c->dev<double>(lay.red);
+        double* red = c->dev<double>(lay.red[k]);
+        I.red = red;
+        I.cons = red + 5 * RED_BLOCKS;
+        I.hist_count = reinterpret_cast<unsigned long long*>(red + 5 * RED_BLOCKS + 8);
+        I.hist = red + 5 * RED_BLOCKS + 9;
+        I.red_blocks = RED_BLOCKS;
+        I.hist_len = p[k].hist_len;
         I.dx = p[k].dx; I.dt = p[k].dt; I.tau = p[k].tau; I.K = p[k].K; I.H = p[k].H;
         I.zeta = p[k].zeta; I.q = p[k].q; I.b = p[k].b_dof; I.a = p[k].vdw_a; I.bw = p[k].vdw_b;
     }
@@ -606,6 +637,7 @@ lb_status lb_init(lb_ctx** out, int n_inst, const lb_params* p, const lb_dvm* dv
             if (p[j].nx == cl.nx && p[j].ny == cl.ny) {
                 order.push_back(j);
                 ++cl.count;
+                if (p[j].hist_len > 0) cl.hist = true;
             }
         c->classes.push_back(cl);
     }
@@ -631,6 +663,16 @@ lb_status lb_init(lb_ctx** out, int n_inst, const lb_params* p, const lb_dvm* dv
         if (e != hipSuccess) {
             ok = false;
             st = fail(LB_E_HIP, "sync failed: %s", hipGetErrorString(e));
+        }
+    }
+    // conservation partials, last result, history counter and ring start at zero (the caller's
+    // workspace is uninitialised); done at init, outside any captured graph
+    for (int k = 0; ok && k < n_inst; ++k) {
+        const size_t bytes = sizeof(double) * (5 * RED_BLOCKS + 8 + 1 + 4 * (size_t)p[k].hist_len);
+        hipError_t e = hipMemsetAsync(c->hinst[k].red, 0, bytes, c->stream);
+        if (e != hipSuccess) {
+            ok = false;
+            st = fail(LB_E_HIP, "clearing conservation buffers: %s", hipGetErrorString(e));
         }
     }
     // tables in float64, rounded to the working precision
@@ -814,22 +856,43 @@ lb_status lb_conservation(lb_ctx* c, int inst, double out[4]) {
     LB_HIP(moments(*c, L, F_A));
     LB_HIP(macro(*c, L, 0, c->j_x1, c->n_x1));
     LB_HIP(macro(*c, L, 1, c->j_y1, c->n_y1));
-    const int64_t nc = c->hinst[inst].ncell;
-    int nb = (int)((nc + 255) / 256);
-    if (nb > RED_BLOCKS) nb = RED_BLOCKS;
-    LB_HIP(c->prec == LB_FP64 ? launch_conserve<double>(c->d_insts(), inst, nb, c->stream)
-                              : launch_conserve<float>(c->d_insts(), inst, nb, c->stream));
-    std::vector<double> part(5 * nb);
-    LB_HIP(hipMemcpyAsync(part.data(), c->dev<double>(c->lay.red), sizeof(double) * 5 * nb,
-                          hipMemcpyDeviceToHost, c->stream));
+    LB_HIP(c->prec == LB_FP64 ? launch_conserve<double>(L, 0) : launch_conserve<float>(L, 0));
+    double r[5];
+    LB_HIP(hipMemcpyAsync(r, c->hinst[inst].cons, sizeof(r), hipMemcpyDeviceToHost, c->stream));
     LB_HIP(hipStreamSynchronize(c->stream));
-    double acc[5] = {0, 0, 0, 0, 0};
-    for (int b = 0; b < nb; ++b)
-        for (int k = 0; k < 5; ++k) acc[k] += part[5 * b + k];
-    const double area = c->p[inst].dx * c->p[inst].dx;
-    for (int k = 0; k < 4; ++k) out[k] = acc[k] * area;
-    if (acc[4] != 0.0 || !std::isfinite(acc[0]) || !std::isfinite(acc[3]))
-        return fail(LB_E_NONFINITE, "instance %d holds %g non-finite cells", inst, acc[4]);
+    for (int k = 0; k < 4; ++k) out[k] = r[k];
+    if (r[4] != 0.0 || !std::isfinite(r[0]) || !std::isfinite(r[3]))
+        return fail(LB_E_NONFINITE, "instance %d holds %g non-finite cells", inst, r[4]);
+    return LB_OK;
+}
+
+lb_status lb_conservation_history(lb_ctx* c, int inst, int max_entries, double* out, int* n_out,
+                                  long long* first_step) {
+    lb_status s = check_inst(c, inst);
+    if (s != LB_OK) return s;
+    if (!out || !n_out || max_entries < 0) return fail(LB_E_ARG, "null output or max_entries < 0");
+    const InstDesc& I = c->hinst[inst];
+    *n_out = 0;
+    if (first_step) *first_step = 0;
+    if (I.hist_len <= 0) return fail(LB_E_STATE, "instance %d keeps no history (hist_len = 0)", inst);
+    unsigned long long count = 0;
+    std::vector<double> ring(4 * (size_t)I.hist_len);
+    LB_HIP(hipMemcpyAsync(&count, I.hist_count, sizeof(count), hipMemcpyDeviceToHost, c->stream));
+    LB_HIP(hipMemcpyAsync(ring.data(), I.hist, ring.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    LB_HIP(hipStreamSynchronize(c->stream));
+    const unsigned long long have = count < (unsigned long long)I.hist_len ? count : (unsigned long long)I.hist_len;
+    const unsigned long long take = have < (unsigned long long)max_entries ? have : (unsigned long long)max_entries;
+    const unsigned long long first = count - take;
+    for (unsigned long long t = 0; t < take; ++t) {
+        const unsigned long long slot = (first + t) % (unsigned long long)I.hist_len;
+        for (int k = 0; k < 4; ++k) out[4 * t + k] = ring[4 * slot + k];
+    }
+    *n_out = (int)take;
+    if (first_step) *first_step = (long long)first;
+    for (unsigned long long t = 0; t < take; ++t)
+        for (int k = 0; k < 4; ++k)
+            if (!std::isfinite(out[4 * t + k]))
+                return fail(LB_E_NONFINITE, "instance %d: non-finite conservation history", inst);
     return LB_OK;
 }
 

@@ -52,9 +52,17 @@ struct InstDesc {
     const void* ky;        // along y, ny words
     const void* twx;       // forward twiddles exp(-2 pi i m / nx), nx complex words
     const void* twy;       // ny complex words
-    double* red;           // reduction partials (float64)
+    double* red;           // conservation partial sums of this instance: RED_BLOCKS x 5 (float64)
+    double* cons;          // last conservation result: mass, momentum x, y, energy, non-finite cells
+    double* hist;          // conservation history ring buffer, hist_len x 4 (float64)
+    unsigned long long* hist_count;   // history entries written so far
+    int32_t red_blocks;    // blocks of the partial-sum kernel
+    int32_t hist_len;      // ring-buffer length (0: no per-step history)
     double dx, dt, tau, K, H, zeta, q, b, a, bw;
 };
+
+// Conservation partial-sum blocks per instance (each block strides over the grid).
+constexpr int RED_BLOCKS = 512;
 
 // Context-wide constants (velocity set and the inverse moment matrix), stored in device
 // memory in both precisions.

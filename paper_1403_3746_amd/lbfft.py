@@ -18,7 +18,7 @@ LB_FP64, LB_FP32 = 0, 1
 _STATUS = {0: "LB_OK", -1: "LB_E_ARG", -2: "LB_E_SIZE", -3: "LB_E_NOMEM", -4: "LB_E_HIP",
            -5: "LB_E_NONFINITE", -6: "LB_E_STATE"}
 
-EXPORTS = ("lb_workspace_bytes", "lb_init", "lb_step", "lb_sync", "lb_moments", "lb_conservation",
+EXPORTS = ("lb_workspace_bytes", "lb_init", "lb_step", "lb_sync", "lb_moments", "lb_conservation", "lb_conservation_history",
            "lb_get_f", "lb_set_f", "lb_force_coefficients", "lb_rhs", "lb_derivative",
            "lb_step_timed", "lb_plan_info", "lb_free", "lb_last_error")
 PASS_NAMES = ("moments", "macro_x1", "macro_y1", "stress", "macro_x2", "macro_y2", "pop_x", "pop_y")
@@ -28,7 +28,8 @@ class lb_params(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("dx", ctypes.c_double),
                 ("dt", ctypes.c_double), ("tau", ctypes.c_double), ("K", ctypes.c_double),
                 ("H", ctypes.c_double), ("zeta", ctypes.c_double), ("q", ctypes.c_double),
-                ("b_dof", ctypes.c_double), ("vdw_a", ctypes.c_double), ("vdw_b", ctypes.c_double)]
+                ("b_dof", ctypes.c_double), ("vdw_a", ctypes.c_double), ("vdw_b", ctypes.c_double),
+                ("hist_len", ctypes.c_int32)]
 
 
 class lb_dvm(ctypes.Structure):
@@ -64,6 +65,8 @@ def load():
     lib.lb_sync.argtypes = [V]
     lib.lb_moments.argtypes = [V, I, dp, dp, dp, dp]
     lib.lb_conservation.argtypes = [V, I, dp]
+    lib.lb_conservation_history.argtypes = [V, I, I, dp, ctypes.POINTER(ctypes.c_int),
+                                            ctypes.POINTER(ctypes.c_longlong)]
     lib.lb_get_f.argtypes = [V, I, dp]
     lib.lb_set_f.argtypes = [V, I, dp]
     lib.lb_force_coefficients.argtypes = [V, I, dp, dp, dp]
@@ -97,7 +100,7 @@ def _dptr(a):
 def make_params(p, nx, ny):
     """lb_params from a parameter dict (keys dx, dt, tau, K, H, zeta, q, b, a, bw)."""
     return lb_params(nx, ny, p["dx"], p["dt"], p["tau"], p["K"], p["H"], p["zeta"], p["q"],
-                     p["b"], p["a"], p["bw"])
+                     p["b"], p["a"], p["bw"], int(p.get("hist", 0)))
 
 
 def make_dvm(d=None):
@@ -151,6 +154,16 @@ def lb_conservation(ctx, inst):
     out = np.empty(4)
     _check(load().lb_conservation(ctx, inst, _dptr(out)))
     return out
+
+
+def lb_conservation_history(ctx, inst, max_entries):
+    """(first_step, array[n, 4]) of the per-step conservation integrals kept on the GPU."""
+    out = np.empty((max(max_entries, 1), 4))
+    n = ctypes.c_int()
+    first = ctypes.c_longlong()
+    _check(load().lb_conservation_history(ctx, inst, max_entries, _dptr(out), ctypes.byref(n),
+                                          ctypes.byref(first)))
+    return first.value, out[: n.value].copy()
 
 
 def lb_get_f(ctx, inst, shape):
@@ -236,6 +249,9 @@ class Sim:
 
     def conservation(self, inst=0):
         return lb_conservation(self.ctx, inst)
+
+    def history(self, inst=0, max_entries=1 << 20):
+        return lb_conservation_history(self.ctx, inst, max_entries)
 
     def get_f(self, inst=0):
         return lb_get_f(self.ctx, inst, self.shapes[inst])

@@ -38,6 +38,9 @@ def test_workspace_bytes_validates_sizes():
         assert lbfft.lb_workspace_bytes([lbfft.make_params(p, nx, ny)], lbfft.LB_FP32) > 0
     bad = dict(p, tau=0.0)
     assert lbfft.lb_workspace_bytes([lbfft.make_params(bad, 64, 64)], lbfft.LB_FP64) == 0
+    assert lbfft.lb_workspace_bytes([lbfft.make_params(dict(p, hist=-1), 64, 64)], lbfft.LB_FP64) == 0
+    with_hist = lbfft.lb_workspace_bytes([lbfft.make_params(dict(p, hist=1000), 64, 64)], lbfft.LB_FP64)
+    assert with_hist >= ok + 1000 * 4 * 8
 
 
 def test_init_rejects_bad_arguments_without_gpu():

@@ -216,3 +216,36 @@ def test_step_timed_matches_graph_step(torch_cuda):
     assert np.array_equal(a.get_f(), b.get_f())
     a.close()
     b.close()
+
+
+def test_conservation_history_matches_oracle(torch_cuda):
+    p = W.base_params(q=-0.004, hist=20)
+    ic = W.smooth_random(48, 32, 17, T0=0.5)
+    sim = _sim([(p, ic)])
+    c0 = sim.conservation()
+    sim.step(10)
+    first, h = sim.history()
+    assert first == 0 and h.shape == (10, 4)
+    assert np.array_equal(h[0], c0)
+    f = model.init_equilibrium(*ic, p)
+    for n in range(10):
+        ref = model.conservation(f, p)
+        assert abs(h[n, 0] - ref[0]) < 1e-12 * abs(ref[0])
+        assert abs(h[n, 1] - ref[1]) < 1e-12 * abs(ref[0]) and abs(h[n, 2] - ref[2]) < 1e-12 * abs(ref[0])
+        assert abs(h[n, 3] - ref[3]) < 1e-11 * abs(ref[3])
+        f = model.rk2_step(f, p)
+    say(f"history mass drift over 10 steps: {h[-1, 0] - h[0, 0]:.3e}")
+    sim.close()
+
+
+def test_conservation_history_ring_wraps(torch_cuda):
+    insts = [(W.base_params(hist=4), W.slab(32, 32, 0.5)), (W.base_params(), W.slab(32, 32, 0.52))]
+    sim = _sim(insts)
+    sim.step(10)
+    first, h = sim.history(0)
+    assert first == 6 and h.shape == (4, 4)
+    from paper_1403_3746_amd import lbfft
+    with pytest.raises(lbfft.LBError) as e:
+        sim.history(1)
+    assert e.value.status == lbfft.LB_E_STATE
+    sim.close()
