@@ -32,15 +32,16 @@ HBM_PEAK_GBS = 8000.0
 # stages (only pop_x differs: 39 words in stage 1, 55 in stage 2 where the base f^n is read).
 ALG_WORDS = {
     "moments": 20,     # read 16 f, write rho, ux, uy, T
-    "macro_x1": 10,    # read rho, T, ux, uy; write 6 x-derivatives
-    "macro_y1": 15,    # read 8 fields; write 7 (d_y terms, lap rho, grad div u)
-    "stress": 17,      # read 13; write S_xx, S_xy, S_yy, C
-    "macro_x2": 4,     # read S_xx, S_xy; write their x-derivatives
-    "macro_y2": 8,     # read S_xy, S_yy, 2 x-derivatives, rho, T; write B_x, B_y
+    "macro_x1": 9,     # read rho, T, ux, uy; write d_x rho, d_xx rho, d_x T, d_x ux, d_x uy
+    "macro_y1": 9,     # read rho, T, ux, uy; write the five y counterparts
+    "stress": 17,      # read 12 derivative/moment fields; write S_xx, S_xy, S_yy, div u, C0
+    "macro_x2": 6,     # read S_xx, S_xy, div u; write their x-derivatives
+    "macro_y2": 6,     # read S_xy, S_yy, div u; write their y-derivatives
+    "finalize": 14,    # read rho, T, grad rho, 4 S derivatives, grad div u, C0; write B_x, B_y, C
     "pop_x": 47,       # read 16 f + 7 coefficients (+16 base in stage 2); write 16
     "pop_y": 36,       # read 12 f + 12 partials; write 12
 }
-WORDS_PER_STEP = 2 * sum(ALG_WORDS.values())   # 314
+WORDS_PER_STEP = 2 * sum(ALG_WORDS.values())   # 328
 
 
 def kernel_source_hash():

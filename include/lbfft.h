@@ -142,17 +142,20 @@ lb_status lb_rhs(lb_ctx* ctx, int inst, double* R);
  * line-FFT kernels through the instance's scratch fields; synchronises. */
 lb_status lb_derivative(lb_ctx* ctx, int inst, int axis, int order, const double* g, double* out);
 
-/* Pass kinds of one Runge-Kutta stage, in launch order (index into lb_step_timed's output). */
+/* Pass kinds of one Runge-Kutta stage, in launch order (index into lb_step_timed's output).
+ * The x and y passes of each macroscopic pair are independent and run concurrently in the
+ * captured step. */
 enum {
     LB_PASS_MOMENTS = 0,   /* moments of f (Sec. 2.1)                                  */
     LB_PASS_MACRO_X1 = 1,  /* x derivatives of rho, T, u (Eq. 3)                       */
-    LB_PASS_MACRO_Y1 = 2,  /* y derivatives, lap rho, grad(div u)                      */
-    LB_PASS_STRESS = 3,    /* stress S and C without C_q (Eq. 2)                       */
-    LB_PASS_MACRO_X2 = 4,  /* x derivatives of S (and q rho T grad T)                  */
-    LB_PASS_MACRO_Y2 = 5,  /* B and C + C_q (Eq. 2)                                    */
-    LB_PASS_POP_X = 6,     /* population x pass: equilibrium, forcing, BGK, RK axpy    */
-    LB_PASS_POP_Y = 7,     /* population y pass                                        */
-    LB_NPASS = 8
+    LB_PASS_MACRO_Y1 = 2,  /* y derivatives of rho, T, u                               */
+    LB_PASS_STRESS = 3,    /* stress S, div u and most of C (Eq. 2)                    */
+    LB_PASS_MACRO_X2 = 4,  /* x derivatives of S, div u (and q rho T grad T)           */
+    LB_PASS_MACRO_Y2 = 5,  /* y derivatives of S, div u (and q rho T grad T)           */
+    LB_PASS_FINALIZE = 6,  /* B and C + C_q (Eq. 2)                                    */
+    LB_PASS_POP_X = 7,     /* population x pass: equilibrium, forcing, BGK, RK axpy    */
+    LB_PASS_POP_Y = 8,     /* population y pass                                        */
+    LB_NPASS = 9
 };
 
 /* Enqueue n_steps Runge-Kutta steps exactly as lb_step does but with direct kernel launches, each

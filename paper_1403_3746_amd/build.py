@@ -10,12 +10,13 @@ import sys
 
 PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
+INCLUDE = os.path.join(os.path.dirname(PKG), "include")
 BUILD = os.environ.get("LBFFT_BUILD_DIR", os.path.join(PKG, "_build"))
 LIB = os.environ.get("LBFFT_OUT", os.path.join(PKG, "liblbfft.so"))
 ARCH = os.environ.get("LBFFT_ARCH", "gfx950")
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
-FLAGS = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall",
+FLAGS = [f"--offload-arch={ARCH}", "-O3", "-std=c++17", "-fPIC", "-Wall", "-I", INCLUDE,
          # packed fp32 instructions are kept out of all device code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops"]
 FLAGS += os.environ.get("LBFFT_EXTRA_FLAGS", "").split()

@@ -3,10 +3,10 @@
 //
 // One Runge-Kutta stage R(f) (Eq. 1, Sec. 2.3) runs as:
 //   moments      pointwise   f -> rho, u, T                              (Sec. 2.1)
-//   macro X1     x lines     d_x, d_xx of rho, T, u                      (Eq. 3)
-//   macro Y1     y lines     d_y terms, lap rho, grad(div u)             (Eq. 3)
-//   stress       pointwise   S, C without C_q, q rho T grad T            (Eq. 2, Sec. 2.2)
-//   macro X2/Y2  x, y lines  B = div S/(rho T), C + C_q                  (Eq. 2)
+//   macro X1|Y1  x, y lines  first and second derivatives of rho, T, u   (Eq. 3) (concurrent)
+//   stress       pointwise   S, div u, q rho T grad T, most of C         (Eq. 2, Sec. 2.2)
+//   macro X2|Y2  x, y lines  derivatives of S, div u, Q                  (Eq. 3) (concurrent)
+//   finalize     pointwise   B = div S/(rho T), C + C_q                  (Eq. 2)
 //   pop X        x lines     per population: v_x d_x f, f^eq, I_i, BGK, RK axpy -> final (axis-x
 //                            populations) or partial (the rest)
 //   pop Y        y lines     per population: add -c v_y d_y f to the partial -> final
@@ -170,61 +170,33 @@ macro_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
     const LB_GLOBAL T* kap = gcast(reinterpret_cast<const T*>(DIR == 0 ? I.kx : I.ky));
     const twptr<T> tw = gcast(reinterpret_cast<const cpx<T>*>(DIR == 0 ? I.twx : I.twy));
 
-    // spectrum of the first input
     cpx<T> X[R], Y[R];
-    load_line<T, DIR, R, TPL>(fieldp<T>(I, J.in[0]), X, line, t, nx, ny, active);
+    load_line<T, DIR, R, TPL>(fieldp<T>(I, J.in), X, line, t, nx, ny, active);
     FFT::run(X, lds, t, tw);
     const T invN = T(1.0 / N);
-    const bool two = J.in[1] >= 0;   // two inputs: a single output from the summed spectra
 #pragma unroll 1
     for (int o = 0; o < 2; ++o) {
-        // select the job slots without runtime indexing (which would go through scratch)
+        // select the job slot without runtime indexing (which would go through scratch)
         const int outf = o == 0 ? J.out[0] : J.out[1];
         if (outf < 0) continue;
-        const int mk0 = o == 0 ? J.mult[0][0] : J.mult[1][0];
-        const int mk1 = o == 0 ? J.mult[0][1] : J.mult[1][1];
-        const int pre = o == 0 ? J.pre[0] : J.pre[1];
-        const int post = o == 0 ? J.post[0] : J.post[1];
-        const int sc = o == 0 ? J.scale[0] : J.scale[1];
+        const int mk = o == 0 ? J.mult[0] : J.mult[1];
 #pragma unroll
-        for (int m = 0; m < R; ++m) Y[m] = spectral_mult<T>(mk0, kap[t + m * TPL], invN, X[m]);
-        if (two) {
-            // X is no longer needed: transform the second input in its place
-            load_line<T, DIR, R, TPL>(fieldp<T>(I, J.in[1]), X, line, t, nx, ny, active);
-            FFT::run(X, lds, t, tw);
-#pragma unroll
-            for (int m = 0; m < R; ++m) {
-                const cpx<T> z = spectral_mult<T>(mk1, kap[t + m * TPL], invN, X[m]);
-                Y[m] = cadd(Y[m], z);
-            }
-        }
+        for (int m = 0; m < R; ++m) Y[m] = spectral_mult<T>(mk, kap[t + m * TPL], invN, X[m]);
         IFFT::run(Y, lds, t, tw);
         if (!active) continue;
         LB_GLOBAL T* out = fieldp<T>(I, outf);
-        const LB_GLOBAL T* prep = fieldp<T>(I, pre < 0 ? 0 : pre);
-        const LB_GLOBAL T* postp = fieldp<T>(I, post < 0 ? 0 : post);
-        const LB_GLOBAL T* rhop = fieldp<T>(I, RHO);
-        const LB_GLOBAL T* tp = fieldp<T>(I, TT);
 #pragma unroll
         for (int m = 0; m < R; ++m) {
-            // compiler fence: bounds how many epilogue loads are hoisted (register pressure)
-            if (m % LB_EPI_GROUP == 0) asm volatile("" ::: "memory");
             const int p = t + m * TPL;
-#pragma unroll
-            for (int h = 0; h < 2; ++h) {
-                if (DIR == 0 && h == 1 && 2 * line + 1 >= ny) continue;
-                const uint32_t e = h == 0 ? LineAddr<DIR>::re(line, p, nx) : LineAddr<DIR>::im(line, p, nx);
-                T val = h == 0 ? Y[m].re : Y[m].im;
-                if (pre >= 0) val += prep[e];
-                if (sc != S_ONE) {
-                    const T rho = rhop[e], T_ = tp[e];
-                    val = sc == S_INV_RHOT ? val / (rho * T_) : val / (rho * T_ * T_);
-                }
-                if (post >= 0) val += postp[e];
-                out[e] = val;
+            if constexpr (DIR == 0) {
+                out[LineAddr<0>::re(line, p, nx)] = Y[m].re;
+                if (2 * line + 1 < ny) out[LineAddr<0>::im(line, p, nx)] = Y[m].im;
+            } else {
+                LB_GLOBAL vec2<T>* o2 = reinterpret_cast<LB_GLOBAL vec2<T>*>(out + LineAddr<1>::re(line, p, nx));
+                o2->a = Y[m].re;
+                o2->b = Y[m].im;
             }
         }
-        if (two) break;
     }
 }
 
@@ -353,7 +325,7 @@ pop_x_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
     const LB_GLOBAL T* tp = fieldp<T>(I, TT);
     const LB_GLOBAL T* bxp = fieldp<T>(I, BX);
     const LB_GLOBAL T* byp = fieldp<T>(I, BY);
-    const LB_GLOBAL T* dcp = fieldp<T>(I, I.q != 0.0 ? CT : C0);
+    const LB_GLOBAL T* dcp = fieldp<T>(I, CT);
 #pragma unroll
     for (int m = 0; m < R; ++m) {
         if (m % LB_EPI_GROUP == 0) asm volatile("" ::: "memory");
@@ -478,18 +450,19 @@ moments_kernel(const InstDesc* __restrict__ insts, const int* __restrict__ ilist
     fieldp<T>(I, TT)[e] = (en / r - ux * ux - uy * uy) / T(I.b);
 }
 
-// Stress S = (P^w - rho T) I + Lambda - zeta (div u) I, the C of Eq. (2) without C_q, and
-// Q = q rho T grad T (Sec. 2.2).
+// Stress S = (P^w - rho T) I + Lambda - zeta (div u) I, div u, Q = q rho T grad T and the part
+// C0 of Eq. (2)'s C that needs no second pass (everything but -K rho grad rho . grad(div u);
+// C_q is added in finalize_kernel) (Sec. 2.2).
 template <typename T>
 __global__ void __launch_bounds__(256)
 stress_kernel(const InstDesc* __restrict__ insts, const int* __restrict__ ilist) {
     LB_POINTWISE_PROLOGUE
     const T rho = fieldp<T>(I, RHO)[e], Tm = fieldp<T>(I, TT)[e];
-    const T rx = fieldp<T>(I, RX)[e], ry = fieldp<T>(I, RY)[e], lap = fieldp<T>(I, LAP)[e];
+    const T rx = fieldp<T>(I, RX)[e], ry = fieldp<T>(I, RY)[e];
+    const T lap = fieldp<T>(I, RXX)[e] + fieldp<T>(I, RYY)[e];
     const T Tx = fieldp<T>(I, TX)[e], Ty = fieldp<T>(I, TY)[e];
     const T uxx = fieldp<T>(I, UXX)[e], uxy = fieldp<T>(I, UXY)[e];   // d_x u_x, d_y u_x
     const T uyx = fieldp<T>(I, UYX)[e], uyy = fieldp<T>(I, UYY)[e];   // d_x u_y, d_y u_y
-    const T gdx = fieldp<T>(I, GDX)[e], gdy = fieldp<T>(I, GDY)[e];
     const T K = T(I.K), H = T(I.H), zeta = T(I.zeta), a = T(I.a), bw = T(I.bw);
 
     const T div = uxx + uyy;
@@ -505,16 +478,34 @@ stress_kernel(const InstDesc* __restrict__ insts, const int* __restrict__ ilist)
     fieldp<T>(I, SXX)[e] = pn + Lxx - zeta * div;
     fieldp<T>(I, SXY)[e] = Lxy;
     fieldp<T>(I, SYY)[e] = pn + Lyy - zeta * div;
+    fieldp<T>(I, DIV)[e] = div;
     const T lam_du = Lxx * uxx + Lxy * uyx + Lxy * uxy + Lyy * uyy;
     const T rgr = rx * (uxx * rx + uyx * ry) + ry * (uxy * rx + uyy * ry);
     const T num = pn * div + lam_du - zeta * div * div + a * rho * rho * div +
-                  K * (T(-0.5) * g2 * div - rho * (rx * gdx + ry * gdy) - rgr);
+                  K * (T(-0.5) * g2 * div - rgr);
     fieldp<T>(I, C0)[e] = num / (T(2) * rT * Tm);
     if (I.q != 0.0) {
         const T qrt = T(I.q) * rT;
         fieldp<T>(I, QX)[e] = qrt * Tx;
         fieldp<T>(I, QY)[e] = qrt * Ty;
     }
+}
+
+// B = div S / (rho T) and C + C_q of Eq. (2) from the second derivative passes:
+//   C = C0 - K rho grad rho . grad(div u) / (2 rho T^2),  C_q = div Q / (rho T^2).
+template <typename T>
+__global__ void __launch_bounds__(256)
+finalize_kernel(const InstDesc* __restrict__ insts, const int* __restrict__ ilist) {
+    LB_POINTWISE_PROLOGUE
+    const T rho = fieldp<T>(I, RHO)[e], Tm = fieldp<T>(I, TT)[e];
+    const T rT = rho * Tm;
+    fieldp<T>(I, BX)[e] = (fieldp<T>(I, DSXX)[e] + fieldp<T>(I, DYSXY)[e]) / rT;
+    fieldp<T>(I, BY)[e] = (fieldp<T>(I, DSXY)[e] + fieldp<T>(I, DYSYY)[e]) / rT;
+    const T rx = fieldp<T>(I, RX)[e], ry = fieldp<T>(I, RY)[e];
+    const T gdx = fieldp<T>(I, GDX)[e], gdy = fieldp<T>(I, GDY)[e];
+    T c = fieldp<T>(I, C0)[e] - T(I.K) * rho * (rx * gdx + ry * gdy) / (T(2) * rT * Tm);
+    if (I.q != 0.0) c += (fieldp<T>(I, DQX)[e] + fieldp<T>(I, DYQY)[e]) / (rT * Tm);
+    fieldp<T>(I, CT)[e] = c;
 }
 
 // Initial populations f = f^eq(rho0, u0, T0), computed in float64 from float64 inputs staged in

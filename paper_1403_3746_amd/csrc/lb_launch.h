@@ -46,6 +46,8 @@ hipError_t launch_moments(const LaunchSet& L, const DvmConst<T>* dvm, int f_fiel
 template <typename T>
 hipError_t launch_stress(const LaunchSet& L);
 template <typename T>
+hipError_t launch_finalize(const LaunchSet& L);
+template <typename T>
 hipError_t launch_init(const LaunchSet& L, const DvmConst<double>* dvm);
 template <typename T>
 hipError_t launch_tables(const InstDesc* insts, int inst, int nx, int ny, hipStream_t s);

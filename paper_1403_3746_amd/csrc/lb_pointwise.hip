@@ -82,6 +82,13 @@ hipError_t launch_stress(const LaunchSet& L) {
 }
 
 template <typename T>
+hipError_t launch_finalize(const LaunchSet& L) {
+    const int64_t nc = (int64_t)L.nx * L.ny;
+    LB_LAUNCH(L, (finalize_kernel<T>), cell_grid(nc, L.ninst), dim3(256), L.insts, L.ilist);
+    return hipGetLastError();
+}
+
+template <typename T>
 hipError_t launch_init(const LaunchSet& L, const DvmConst<double>* dvm) {
     const int64_t nc = (int64_t)L.nx * L.ny;
     hipLaunchKernelGGL((init_kernel<T>), cell_grid(nc, L.ninst), dim3(256), 0, L.stream,
@@ -123,6 +130,7 @@ hipError_t launch_from_f64(const double* src, void* dst, int64_t n, hipStream_t 
 #define LB_INST(T)                                                                         \
     template hipError_t launch_moments<T>(const LaunchSet&, const DvmConst<T>*, int);      \
     template hipError_t launch_stress<T>(const LaunchSet&);                                \
+    template hipError_t launch_finalize<T>(const LaunchSet&);                              \
     template hipError_t launch_init<T>(const LaunchSet&, const DvmConst<double>*);         \
     template hipError_t launch_tables<T>(const InstDesc*, int, int, int, hipStream_t);     \
     template hipError_t launch_conserve<T>(const LaunchSet&, int);                         \

@@ -12,7 +12,7 @@
 #include <string>
 #include <vector>
 
-#include "../../include/lbfft.h"
+#include "lbfft.h"
 #include "lb_launch.h"
 #include "lb_types.h"
 
@@ -188,87 +188,48 @@ struct lb_ctx {
 
 namespace {
 
-JobDesc job(int in0, int out0, int m0, int out1 = -1, int m1 = M_NONE) {
+JobDesc job(int in, int out0, int m0, int out1 = -1, int m1 = M_NONE, int flag_q = 0) {
     JobDesc j;
     std::memset(&j, 0, sizeof(j));
-    j.in[0] = (int16_t)in0;
-    j.in[1] = -1;
+    j.in = (int16_t)in;
     j.out[0] = (int16_t)out0;
     j.out[1] = (int16_t)out1;
-    j.pre[0] = j.pre[1] = j.post[0] = j.post[1] = -1;
-    j.mult[0][0] = (int8_t)m0;
-    j.mult[1][0] = (int8_t)m1;
-    j.mult[0][1] = j.mult[1][1] = M_NONE;
-    j.scale[0] = j.scale[1] = S_ONE;
+    j.mult[0] = (int8_t)m0;
+    j.mult[1] = (int8_t)m1;
+    j.flag_q = (int8_t)flag_q;
     return j;
 }
 
-// Job tables of the four macroscopic line passes of one stage.
+// Job tables of the four macroscopic line passes of one stage.  Every job is one input; the
+// first and second derivatives of rho share a job (one forward transform, two inverse).
 void build_jobs(lb_ctx& c) {
     auto& J = c.jobs;
     J.clear();
-    // X1: d_x, d_xx of rho; d_x T; d_x, d_xx of u_x; d_x u_y
+    // X1 / Y1: first (and for rho second) derivatives of the moments
     c.j_x1 = (int)J.size();
     J.push_back(job(RHO, RX, M_D, RXX, M_DD));
     J.push_back(job(TT, TX, M_D));
-    J.push_back(job(UX, UXX, M_D, UXXX, M_DD));
+    J.push_back(job(UX, UXX, M_D));
     J.push_back(job(UY, UYX, M_D));
     c.n_x1 = (int)J.size() - c.j_x1;
-    // Y1: d_y rho, lap rho = d_xx rho + d_yy rho, d_y T, d_y u_x, d_y u_y,
-    //     d_x(div u) = d_xx u_x + d_y (d_x u_y), d_y(div u) = d_y (d_x u_x) + d_yy u_y
     c.j_y1 = (int)J.size();
-    {
-        JobDesc j = job(RHO, RY, M_D, LAP, M_DD);
-        j.pre[1] = RXX;
-        J.push_back(j);
-    }
+    J.push_back(job(RHO, RY, M_D, RYY, M_DD));
     J.push_back(job(TT, TY, M_D));
     J.push_back(job(UX, UXY, M_D));
     J.push_back(job(UY, UYY, M_D));
-    {
-        JobDesc j = job(UYX, GDX, M_D);
-        j.pre[0] = UXXX;
-        J.push_back(j);
-    }
-    {
-        JobDesc j = job(UXX, GDY, M_D);
-        j.in[1] = UY;
-        j.mult[0][1] = M_DD;
-        J.push_back(j);
-    }
     c.n_y1 = (int)J.size() - c.j_y1;
-    // X2: d_x S_xx, d_x S_xy, d_x Q_x (q != 0 only)
+    // X2 / Y2: derivatives of the stress, of div u and of Q = q rho T grad T (q != 0 only)
     c.j_x2 = (int)J.size();
     J.push_back(job(SXX, DSXX, M_D));
     J.push_back(job(SXY, DSXY, M_D));
-    {
-        JobDesc j = job(QX, DQX, M_D);
-        j.flag_q = 1;
-        J.push_back(j);
-    }
+    J.push_back(job(DIV, GDX, M_D));
+    J.push_back(job(QX, DQX, M_D, -1, M_NONE, 1));
     c.n_x2 = (int)J.size() - c.j_x2;
-    // Y2: B = div S / (rho T);  C + C_q = C0 + div Q / (rho T^2)
     c.j_y2 = (int)J.size();
-    {
-        JobDesc j = job(SXY, BX, M_D);
-        j.pre[0] = DSXX;
-        j.scale[0] = S_INV_RHOT;
-        J.push_back(j);
-    }
-    {
-        JobDesc j = job(SYY, BY, M_D);
-        j.pre[0] = DSXY;
-        j.scale[0] = S_INV_RHOT;
-        J.push_back(j);
-    }
-    {
-        JobDesc j = job(QY, CT, M_D);
-        j.pre[0] = DQX;
-        j.scale[0] = S_INV_RHOT2;
-        j.post[0] = C0;
-        j.flag_q = 1;
-        J.push_back(j);
-    }
+    J.push_back(job(SXY, DYSXY, M_D));
+    J.push_back(job(SYY, DYSYY, M_D));
+    J.push_back(job(DIV, GDY, M_D));
+    J.push_back(job(QY, DYQY, M_D, -1, M_NONE, 1));
     c.n_y2 = (int)J.size() - c.j_y2;
     // lb_derivative: SCR0 -> SCR1
     c.j_dx = (int)J.size();
@@ -308,6 +269,10 @@ hipError_t stress(const lb_ctx& c, const LaunchSet& L) {
     return c.prec == LB_FP64 ? launch_stress<double>(L) : launch_stress<float>(L);
 }
 
+hipError_t finalize(const lb_ctx& c, const LaunchSet& L) {
+    return c.prec == LB_FP64 ? launch_finalize<double>(L) : launch_finalize<float>(L);
+}
+
 // Optional timing hook: supplies a start/stop event pair for every launch of a pass.
 struct PassHook {
     virtual bool events(int pass, hipEvent_t* start, hipEvent_t* stop) = 0;
@@ -336,6 +301,7 @@ hipError_t run_pass(const lb_ctx& c, const LaunchSet& L, int kind, StageArgs st)
         case LB_PASS_STRESS: return stress(c, L);
         case LB_PASS_MACRO_X2: return macro(c, L, 0, c.j_x2, c.n_x2);
         case LB_PASS_MACRO_Y2: return macro(c, L, 1, c.j_y2, c.n_y2);
+        case LB_PASS_FINALIZE: return finalize(c, L);
         case LB_PASS_POP_X: return pop_x(c, L, st);
         case LB_PASS_POP_Y: return pop_y(c, L, st);
     }
@@ -345,7 +311,7 @@ hipError_t run_pass(const lb_ctx& c, const LaunchSet& L, int kind, StageArgs st)
 // Moments and the force coefficients B, C (+ C_q) of the population block f_field.
 hipError_t force_passes(const lb_ctx& c, const LaunchSet& L, int f_field) {
     StageArgs st{f_field, -1, -1, 0.0, 0};
-    for (int k = LB_PASS_MOMENTS; k <= LB_PASS_MACRO_Y2; ++k) {
+    for (int k = LB_PASS_MOMENTS; k <= LB_PASS_FINALIZE; ++k) {
         hipError_t e = run_pass(c, L, k, st);
         if (e != hipSuccess) return e;
     }
@@ -358,19 +324,27 @@ hipError_t pop_passes(const lb_ctx& c, const LaunchSet& L, StageArgs st) {
     return pop_y(c, L, st);
 }
 
-// One Runge-Kutta stage of the instances of one size class on stream s.
+hipError_t launch_pass(const lb_ctx& c, const lb_ctx::Class& cl, hipStream_t s, int k,
+                       StageArgs st, PassHook* hook) {
+    LaunchSet L = set_of(c, cl);
+    L.stream = s;
+    if (hook && !hook->events(k, &L.ev_start, &L.ev_stop)) return hipErrorInvalidValue;
+    return run_pass(c, L, k, st);
+}
+
+// One Runge-Kutta stage of the instances of one size class on stream s:
+//   moments -> X1 -> Y1 -> stress -> X2 -> Y2 -> finalize -> pop x -> pop y.
+// (X1/Y1 and X2/Y2 are independent; they are issued in order on one stream.)
 hipError_t enqueue_class_stage(const lb_ctx& c, const lb_ctx::Class& cl, hipStream_t s,
                                StageArgs st, PassHook* hook) {
     for (int k = 0; k < LB_NPASS; ++k) {
-        LaunchSet L = set_of(c, cl);
-        L.stream = s;
-        if (hook && !hook->events(k, &L.ev_start, &L.ev_stop)) return hipErrorInvalidValue;
-        hipError_t e = run_pass(c, L, k, st);
+        hipError_t e = launch_pass(c, cl, s, k, st, hook);
         if (e != hipSuccess) return e;
         // per-step FP64 conservation of the state f^n: its moments and d_x rho, d_y rho exist
         // after the first stage's y derivative pass
         if (k == LB_PASS_MACRO_Y1 && cl.hist && st.f_field == F_A && st.use_dt) {
-            L.ev_start = L.ev_stop = nullptr;
+            LaunchSet L = set_of(c, cl);
+            L.stream = s;
             e = c.prec == LB_FP64 ? launch_conserve<double>(L, 1) : launch_conserve<float>(L, 1);
             if (e != hipSuccess) return e;
         }
@@ -389,7 +363,7 @@ hipError_t enqueue_class_step(const lb_ctx& c, const lb_ctx::Class& cl, hipStrea
     return enqueue_class_stage(c, cl, s, s2, hook);
 }
 
-// One step of every instance on stream s, size classes one after the other.
+// One step of every instance on stream s, size classes one after the other, all on s.
 hipError_t enqueue_step(const lb_ctx& c, hipStream_t s, PassHook* hook = nullptr) {
     for (const auto& cl : c.classes) {
         hipError_t e = enqueue_class_step(c, cl, s, hook);
@@ -398,8 +372,8 @@ hipError_t enqueue_step(const lb_ctx& c, hipStream_t s, PassHook* hook = nullptr
     return hipSuccess;
 }
 
-// One step captured with the size classes as parallel branches: the capture stream forks to one
-// stream per class (default priority) and joins them again.
+// One step captured as a graph with the size classes as parallel branches: the capture stream
+// forks to one stream per class (default priority) and joins them again.
 hipError_t capture_step(const lb_ctx& c, hipStream_t cs, std::vector<hipStream_t>& br,
                         std::vector<hipEvent_t>& ev) {
     if (c.classes.size() <= 1) return enqueue_step(c, cs);
@@ -914,10 +888,9 @@ lb_status lb_force_coefficients(lb_ctx* c, int inst, double* Bx, double* By, dou
     lb_status s = check_inst(c, inst);
     if (s != LB_OK) return s;
     LB_HIP(force_passes(*c, set_one(*c, inst, c->stream), F_A));
-    const int ct = c->p[inst].q != 0.0 ? CT : C0;
     if (Bx && (s = field_to_host(c, inst, BX, Bx)) != LB_OK) return s;
     if (By && (s = field_to_host(c, inst, BY, By)) != LB_OK) return s;
-    if (C && (s = field_to_host(c, inst, ct, C)) != LB_OK) return s;
+    if (C && (s = field_to_host(c, inst, CT, C)) != LB_OK) return s;
     return LB_OK;
 }
 

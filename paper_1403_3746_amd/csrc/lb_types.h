@@ -12,35 +12,28 @@ enum FieldId : int {
     F_B = 16,    // midpoint state f^{n+1/2}, 16 fields (also the rhs output of lb_rhs)
     F_P = 32,    // per-population partial updates between the x and y passes, 16 fields
     RHO = 48, UX, UY, TT,                        // moments (Sec. 2.1)
-    RX, RXX, TX, UXX, UYX, UXXX,                 // x-pass outputs: d_x rho, d_xx rho, d_x T,
-                                                 // d_x u_x, d_x u_y, d_xx u_x
-    RY, LAP, TY, UXY, UYY, GDX, GDY,             // y-pass outputs: d_y rho, lap rho, d_y T,
-                                                 // d_y u_x, d_y u_y, grad(div u)
-    SXX, SXY, SYY, C0, QX, QY,                   // stress S, C without C_q, q rho T grad T
-    DSXX, DSXY, DQX,                             // d_x of S_xx, S_xy, Q_x
+    RX, RXX, TX, UXX, UYX,                       // x pass 1: d_x rho, d_xx rho, d_x T, d_x u_x, d_x u_y
+    RY, RYY, TY, UXY, UYY,                       // y pass 1: d_y rho, d_yy rho, d_y T, d_y u_x, d_y u_y
+    SXX, SXY, SYY, DIV, C0, QX, QY,              // stress S, div u, C without the grad(div u) and
+                                                 // C_q terms, Q = q rho T grad T
+    DSXX, DSXY, GDX, DQX,                        // x pass 2: d_x of S_xx, S_xy, div u, Q_x
+    DYSXY, DYSYY, GDY, DYQY,                     // y pass 2: d_y of S_xy, S_yy, div u, Q_y
     BX, BY, CT,                                  // B and C + C_q of Eq. (2)
     SCR0, SCR1,                                  // scratch for lb_derivative
     NFIELDS
 };
 
-// Spectral multiplier kinds of a job term.
+// Spectral multiplier kinds of a job.
 enum MultKind : int8_t { M_NONE = 0, M_D = 1, M_DD = 2 };
-// Scale applied after the inverse transform (and the pre-addend).
-enum ScaleKind : int8_t { S_ONE = 0, S_INV_RHOT = 1, S_INV_RHOT2 = 2 };
 
-// One job of a macroscopic line pass:
-//   out[o] = post[o] + scale[o] * (pre[o] + IFFT( sum_k mult[o][k] * FFT(in[k]) ))
-// along the pass direction.  Unused slots hold -1 / M_NONE.  flag_q: the job only runs for
-// instances with q != 0.
+// One job of a macroscopic line pass: out[o] = IFFT(mult[o] * FFT(in)) along the pass direction,
+// o = 0, 1 (out[1] = -1 when unused).  flag_q: the job only runs for instances with q != 0.
 struct JobDesc {
-    int16_t in[2];
+    int16_t in;
     int16_t out[2];
-    int16_t pre[2];
-    int16_t post[2];
-    int8_t mult[2][2];
-    int8_t scale[2];
+    int8_t mult[2];
     int8_t flag_q;
-    int8_t pad[3];
+    int8_t pad;
 };
 
 // Per-instance descriptor, stored in device memory.

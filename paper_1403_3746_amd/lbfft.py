@@ -21,7 +21,8 @@ _STATUS = {0: "LB_OK", -1: "LB_E_ARG", -2: "LB_E_SIZE", -3: "LB_E_NOMEM", -4: "L
 EXPORTS = ("lb_workspace_bytes", "lb_init", "lb_step", "lb_sync", "lb_moments", "lb_conservation", "lb_conservation_history",
            "lb_get_f", "lb_set_f", "lb_force_coefficients", "lb_rhs", "lb_derivative",
            "lb_step_timed", "lb_plan_info", "lb_free", "lb_last_error")
-PASS_NAMES = ("moments", "macro_x1", "macro_y1", "stress", "macro_x2", "macro_y2", "pop_x", "pop_y")
+PASS_NAMES = ("moments", "macro_x1", "macro_y1", "stress", "macro_x2", "macro_y2", "finalize",
+              "pop_x", "pop_y")
 
 
 class lb_params(ctypes.Structure):
