@@ -25,7 +25,10 @@
 #define LB_YSEG 128      // bytes of each row a y-pass tile covers (2 * lines per block * word)
 #endif
 #ifndef LB_POPX_WAVES
-#define LB_POPX_WAVES 4  // waves per SIMD the single-population x pass must fit (register budget)
+#define LB_POPX_WAVES 4  // waves per SIMD the single-population FP32 x pass must fit (register budget)
+#endif
+#ifndef LB_POPX_WAVES_F64
+#define LB_POPX_WAVES_F64 3  // the same for FP64 (fewer: its epilogue holds twice the registers)
 #endif
 
 namespace lbfft {
@@ -107,6 +110,38 @@ struct vec2 {
 template <typename T>
 __device__ __forceinline__ LB_GLOBAL T* fieldp(const InstDesc& I, int id) {
     return gcast(reinterpret_cast<T*>(I.base) + (int64_t)id * I.ncell);
+}
+
+// The instance's field arena through one buffer resource (an SGPR descriptor).  A field is a
+// uniform 32-bit byte offset (soffset) and a cell a per-lane 32-bit byte offset (voffset), so an
+// access needs no 64-bit address arithmetic and a field costs one SGPR instead of four.  The
+// runtime keeps the arena (NFIELDS * ncell * sizeof(T) bytes) below 2^32 bytes.
+struct Arena {
+    __amdgpu_buffer_rsrc_t r;
+};
+
+template <typename T>
+__device__ __forceinline__ Arena arena(const InstDesc& I) {
+    const uint32_t bytes = (uint32_t)NFIELDS * (uint32_t)I.ncell * (uint32_t)sizeof(T);
+    return Arena{__builtin_amdgcn_make_buffer_rsrc(I.base, 0, (int)bytes, 0x00020000)};
+}
+template <typename T>
+__device__ __forceinline__ uint32_t fofs(const InstDesc& I, int id) {
+    return (uint32_t)id * (uint32_t)I.ncell * (uint32_t)sizeof(T);
+}
+
+__device__ __forceinline__ double bload(Arena a, uint32_t fo, uint32_t e, double) {
+    return __builtin_bit_cast(double, __builtin_amdgcn_raw_buffer_load_b64(a.r, e * 8u, fo, 0));
+}
+__device__ __forceinline__ float bload(Arena a, uint32_t fo, uint32_t e, float) {
+    return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(a.r, e * 4u, fo, 0));
+}
+__device__ __forceinline__ void bstore(Arena a, uint32_t fo, uint32_t e, double v) {
+    using V2 = decltype(__builtin_amdgcn_raw_buffer_load_b64(a.r, 0, 0, 0));
+    __builtin_amdgcn_raw_buffer_store_b64(__builtin_bit_cast(V2, v), a.r, e * 8u, fo, 0);
+}
+__device__ __forceinline__ void bstore(Arena a, uint32_t fo, uint32_t e, float v) {
+    __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), a.r, e * 4u, fo, 0);
 }
 
 // Addressing of the two real lines packed into complex line `line` at position p.
@@ -263,6 +298,101 @@ __device__ __forceinline__ T feq_pop(const DvmConst<T>& D, int i, T rho, T ux, T
 }
 
 // ---------------------------------------------------------------------------------------
+// Epilogue of the population x pass for one thread: its R positions of the block's two rows,
+// cell k = 2 m + h (position m, row h).  Per cell it reads the seven macroscopic inputs (rho, u_x,
+// u_y, T, B_x, B_y, C) and the P base values, and writes P results.  The cells run in groups of
+// LB_EPI_CELLS_F64 / _F32 whose reads are issued one group ahead of the group being computed and stored, so a
+// thread has the next group's loads in flight instead of waiting on each cell's loads in turn.
+#ifndef LB_EPI_CELLS_F64
+#define LB_EPI_CELLS_F64 1
+#endif
+#ifndef LB_EPI_CELLS_F32
+#define LB_EPI_CELLS_F32 4
+#endif
+template <typename T, int R, int TPL, int P>
+struct PopXEpi {
+    static constexpr int NV = 7 + P;   // values read per cell
+    static constexpr int G = sizeof(T) == 8 ? LB_EPI_CELLS_F64 : LB_EPI_CELLS_F32;
+    static constexpr int NG = 2 * R / G;
+    static_assert((2 * R) % G == 0, "cells per group must divide the cells per thread");
+    const DvmConst<T>& D;
+    const int (&pop)[P];
+    Arena a;
+    const uint32_t (&cf)[7];      // field offsets of rho, u_x, u_y, T, B_x, B_y, C
+    const uint32_t (&basep)[P];
+    const uint32_t (&outp)[P];
+    bool has_base;
+    int line, t, nx;
+    bool row1;   // the block's second row exists (odd ny leaves the last pair with one row)
+    T b, c, inv_tau;
+
+    __device__ __forceinline__ uint32_t cell(int k) const {
+        const int m = k >> 1, h = k & 1;
+        // the missing second row of an odd grid reads row 0's cell and stores nothing
+        return (uint32_t)(2 * line + (h & (int)row1)) * nx + t + m * TPL;
+    }
+    __device__ __forceinline__ void load(int g, T (&v)[G][NV]) const {
+#pragma unroll
+        for (int j = 0; j < G; ++j) {
+            const uint32_t e = cell(g * G + j);
+#pragma unroll
+            for (int f = 0; f < 7; ++f) v[j][f] = bload(a, cf[f], e, T());
+#pragma unroll
+            for (int q = 0; q < P; ++q) v[j][7 + q] = bload(a, basep[q], e, T());
+        }
+    }
+    // rotu: the block's pairs are y mirrors (v_x = 0); their equilibria are those of the x-mirror
+    // pairs rot(i) at the turned velocity (u_y, -u_x)
+    __device__ __forceinline__ void run(const cpx<T> (&X)[P][R], bool rotu) const {
+        T v[2][G][NV];
+        load(0, v[0]);
+#pragma unroll
+        for (int g = 0; g < NG; ++g) {
+            if (g + 1 < NG) load(g + 1, v[(g + 1) & 1]);
+#pragma unroll
+            for (int j = 0; j < G; ++j) {
+                const int k = g * G + j, m = k >> 1, h = k & 1;
+                const T* x = v[g & 1][j];
+                const T rho = x[0], ux = x[1], uy = x[2], Tm = x[3], Bx = x[4], By = x[5], Dc = x[6];
+                T mq[16];
+                // BGK gain and forcing: f^eq/tau + I = f^eq [1/tau - A - B.(v - u) - D |v - u|^2]
+                // with A = -2 D T; expanded in v: h0 + hx v_x + hy v_y + hv |v|^2.
+                const T h0 = inv_tau + T(2) * Dc * Tm + Bx * ux + By * uy - Dc * (ux * ux + uy * uy);
+                const T hx = T(2) * Dc * ux - Bx, hy = T(2) * Dc * uy - By, hv = -Dc;
+                T fe[P];
+                if constexpr (P == 1) {
+                    meq_unit(ux, uy, Tm, b, mq);
+                    fe[0] = feq_dot(D, pop[0], rho, mq);
+                } else {
+                    meq_unit(rotu ? uy : ux, rotu ? -ux : uy, Tm, b, mq);
+#pragma unroll
+                    for (int q = 0; q < P; q += 2)
+                        feq_mirror_pair<T, 0>(D, rotu ? D.rot[pop[q]] : pop[q], rho, mq, fe[q], fe[q + 1]);
+                }
+                const uint32_t e = cell(k);
+#pragma unroll
+                for (int q = 0; q < P; ++q) {
+                    const int i = pop[q];
+                    const T gq = h0 + hx * D.vx[i] + hy * D.vy[i] + hv * (D.w[i] - D.eta2[i]);
+                    const T lin = h == 0 ? X[q][m].re : X[q][m].im;
+                    const T base = has_base ? x[7 + q] : T(0);
+                    const T out = base + lin + c * (fe[q] * gq);
+                    if (h == 0 || row1) bstore(a, outp[q], e, out);
+                }
+            }
+        }
+    }
+};
+
+// Minimum waves per SIMD the population x pass is compiled for: the register budget.  Lines of
+// 3 * 2^a points hold 12 elements per thread instead of 8 and get one wave less.
+template <typename T>
+constexpr int popx_waves(int N, int P) {
+    const int w = (sizeof(T) == 8 ? LB_POPX_WAVES_F64 : LB_POPX_WAVES) / P - (default_R(N) == 12 ? 1 : 0);
+    return w > 1 ? w : 1;
+}
+
+// ---------------------------------------------------------------------------------------
 // Population x pass: one block = (instance, tile of row pairs, P populations).  For each
 // population i of the block (D.xorder[job*P + q]):
 //   out = base + c [ -v_x D_x f - (f - f^eq)/tau + I ]
@@ -271,7 +401,7 @@ __device__ __forceinline__ T feq_pop(const DvmConst<T>& D, int i, T rho, T ux, T
 // the equilibrium moments and the coefficient loads of a cell are shared by the P populations.
 template <typename T, int N, int P>
 __global__ void __launch_bounds__((LineCfg<T, N, 0>::WG))
-__attribute__((amdgpu_waves_per_eu(LB_POPX_WAVES / P > 1 ? LB_POPX_WAVES / P : 1)))
+__attribute__((amdgpu_waves_per_eu(popx_waves<T>(N, P))))
 pop_x_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, int ngroups,
            int ntiles, const DvmConst<T>* __restrict__ dvm, StageArgs st) {
     using C = LineCfg<T, N, 0>;
@@ -294,13 +424,17 @@ pop_x_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
     const LB_GLOBAL T* kap = gcast(reinterpret_cast<const T*>(I.kx));
     const T invN = T(1.0 / N);
 
-    // X[q] <- -c v_x D_x f_i - (c/tau) f_i on the block's two rows
+    // X[q] <- -c v_x D_x f_i - (c/tau) f_i on the block's two rows; all P lines are loaded
+    // before the first transform so their memory latencies overlap
     cpx<T> X[P][R];
+#pragma unroll
+    for (int q = 0; q < P; ++q)
+        load_line<T, 0, R, TPL>(fieldp<T>(I, st.f_field + D.xorder[w.job * P + q]), X[q], line, t,
+                                nx, ny, active);
 #pragma unroll
     for (int q = 0; q < P; ++q) {
         const int i = D.xorder[w.job * P + q];
         const T vx = D.vx[i];
-        load_line<T, 0, R, TPL>(fieldp<T>(I, st.f_field + i), X[q], line, t, nx, ny, active);
         if (vx != T(0)) {
             LineFFT<T, N, R, false>::run(X[q], lds, t, tw);
             const T s = -c * vx * invN, mr = -ct * invN;
@@ -317,57 +451,27 @@ pop_x_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
         }
     }
     if (!active) return;
-    const T b = T(I.b);
+    // keep the epilogue's loads out of the transforms above (their registers would be live there)
+    asm volatile("" ::: "memory");
+    int pop[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) pop[q] = D.xorder[w.job * P + q];
     const bool has_base = st.base_field >= 0;
-    const LB_GLOBAL T* rhop = fieldp<T>(I, RHO);
-    const LB_GLOBAL T* uxp = fieldp<T>(I, UX);
-    const LB_GLOBAL T* uyp = fieldp<T>(I, UY);
-    const LB_GLOBAL T* tp = fieldp<T>(I, TT);
-    const LB_GLOBAL T* bxp = fieldp<T>(I, BX);
-    const LB_GLOBAL T* byp = fieldp<T>(I, BY);
-    const LB_GLOBAL T* dcp = fieldp<T>(I, CT);
+    const uint32_t cf[7] = {fofs<T>(I, RHO), fofs<T>(I, UX), fofs<T>(I, UY), fofs<T>(I, TT),
+                            fofs<T>(I, BX), fofs<T>(I, BY), fofs<T>(I, CT)};
+    uint32_t basep[P], outp[P];
 #pragma unroll
-    for (int m = 0; m < R; ++m) {
-        if (m % LB_EPI_GROUP == 0) asm volatile("" ::: "memory");
-        const int p = t + m * TPL;
-#pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            if (h == 1 && 2 * line + 1 >= ny) continue;
-            const uint32_t e = (uint32_t)(2 * line + h) * nx + p;
-            const T rho = rhop[e], ux = uxp[e], uy = uyp[e], Tm = tp[e];
-            const T Bx = bxp[e], By = byp[e], Dc = dcp[e];
-            T mq[16];
-            meq_unit(ux, uy, Tm, b, mq);
-            // I_i = -[A + B.(v_i - u) + D |v_i - u|^2] f^eq_i with A = -2 D T
-            const T g0 = T(-2) * Dc * Tm;
-            T fe[P];
-            if constexpr (P == 1) {
-                fe[0] = feq_dot(D, D.xorder[w.job], rho, mq);
-            } else {
-#pragma unroll
-                for (int q = 0; q < P; q += 2) {
-                    const int i0 = D.xorder[w.job * P + q];
-                    // pairs of populations with v_x != 0 are x mirrors, the others y mirrors
-                    if (D.vx[i0] != T(0))
-                        feq_mirror_pair<T, 0>(D, i0, rho, mq, fe[q], fe[q + 1]);
-                    else
-                        feq_mirror_pair<T, 1>(D, i0, rho, mq, fe[q], fe[q + 1]);
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < P; ++q) {
-                const int i = D.xorder[w.job * P + q];
-                const T vx = D.vx[i], vy = D.vy[i];
-                const T cx = vx - ux, cy = vy - uy;
-                const T force = -(g0 + Bx * cx + By * cy + Dc * (cx * cx + cy * cy)) * fe[q];
-                const T lin = h == 0 ? X[q][m].re : X[q][m].im;
-                const T base = has_base ? fieldp<T>(I, st.base_field + i)[e] : T(0);
-                // out may equal the base block (second stage writes f^{n+1} over f^n per cell)
-                LB_GLOBAL T* out = fieldp<T>(I, (vy == T(0) ? st.out_field : F_P) + i);
-                out[e] = base + lin + c * (force + fe[q] * inv_tau);
-            }
-        }
+    for (int q = 0; q < P; ++q) {
+        // without a base (the bare right-hand side) the partial block is read and discarded
+        basep[q] = fofs<T>(I, has_base ? st.base_field + pop[q] : F_P + pop[q]);
+        // out may equal the base block (second stage writes f^{n+1} over f^n per cell)
+        outp[q] = fofs<T>(I, (D.vy[pop[q]] == T(0) ? st.out_field : F_P) + pop[q]);
     }
+    const bool row1 = 2 * line + 1 < ny;
+    const PopXEpi<T, R, TPL, P> epi{D, pop, arena<T>(I), cf, basep, outp, has_base, line, t, nx, row1,
+                                    T(I.b), c, inv_tau};
+    // pairs of populations with v_x != 0 are x mirrors, the others y mirrors (uniform per block)
+    epi.run(X, P > 1 && D.vx[pop[0]] == T(0));
 }
 
 // Population y pass: one block = (instance, tile of column pairs, population i with v_y != 0).

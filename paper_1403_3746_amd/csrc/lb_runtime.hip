@@ -53,6 +53,11 @@ bool line_ok(int n) {
 
 bool grid_ok(int nx, int ny) { return line_ok(nx) && (line_ok(ny) || ny == 1 || ny == 2); }
 
+// The kernels address an instance's field arena through one buffer descriptor with 32-bit byte
+// offsets, so the largest arena (2048 x 2048 cells in FP64) must stay below 2^32 bytes.
+static_assert((unsigned long long)NFIELDS * 2048 * 2048 * 8 < (1ull << 32),
+              "field arena of the largest grid exceeds 32-bit buffer offsets");
+
 size_t word_bytes(lb_precision p) { return p == LB_FP64 ? 8 : 4; }
 
 // Workspace layout.  Header: InstDesc[n], DvmConst<double>, DvmConst<float>, job tables,
@@ -132,6 +137,7 @@ bool build_dvm(const lb_dvm& d, DvmConst<double>& D) {
             D.vy[i] = speed[ring] * u[k][1];
             const double eta = ring == 0 ? d.eta0 : 0.0;
             D.w[i] = D.vx[i] * D.vx[i] + D.vy[i] * D.vy[i] + eta * eta;
+            D.eta2[i] = eta * eta;
         }
     double A[16][16];
     for (int i = 0; i < 16; ++i) {
@@ -544,6 +550,7 @@ lb_status lb_init(lb_ctx** out, int n_inst, const lb_params* p, const lb_dvm* dv
         c->dvm32.vx[i] = (float)c->dvm64.vx[i];
         c->dvm32.vy[i] = (float)c->dvm64.vy[i];
         c->dvm32.w[i] = (float)c->dvm64.w[i];
+        c->dvm32.eta2[i] = (float)c->dvm64.eta2[i];
         for (int j = 0; j < 16; ++j) c->dvm32.cinv[i][j] = (float)c->dvm64.cinv[i][j];
     }
     for (int i = 0; i < 16; ++i)
@@ -572,6 +579,21 @@ lb_status lb_init(lb_ctx** out, int n_inst, const lb_params* p, const lb_dvm* dv
                 c->dvm64.xorder[k++] = j;
             }
         for (int i = 0; i < 16; ++i) c->dvm32.xorder[i] = c->dvm64.xorder[i];
+    }
+    // quarter-turn partner of each population: f^eq_i(u) = f^eq_rot(i)(u_y, -u_x) on a velocity
+    // set closed under quarter turns, which lets the x pass form the equilibria of a y-mirror pair
+    // with the x-mirror split of the turned pair
+    for (int i = 0; i < 16; ++i) {
+        int j = -1;
+        for (int m = 0; m < 16; ++m)
+            if (c->dvm64.vx[m] == c->dvm64.vy[i] && c->dvm64.vy[m] == -c->dvm64.vx[i] &&
+                c->dvm64.eta2[m] == c->dvm64.eta2[i])
+                j = m;
+        if (j < 0) {
+            delete c;
+            return fail(LB_E_ARG, "velocity set is not closed under quarter turns");
+        }
+        c->dvm64.rot[i] = c->dvm32.rot[i] = j;
     }
     build_jobs(*c);
 

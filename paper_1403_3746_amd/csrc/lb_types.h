@@ -62,9 +62,11 @@ constexpr int RED_BLOCKS = 512;
 template <typename T>
 struct DvmConst {
     T vx[16], vy[16], w[16];   // w = v^2 + eta^2
+    T eta2[16];                // eta^2
     T cinv[16][16];            // inverse of the 16x16 moment matrix of the seven kinetic moments
     int xorder[16];            // population order of the x pass: populations with v_x != 0 first,
                                // grouped so that a block of P consecutive entries shares its FFT load
+    int rot[16];               // population whose velocity is v_i turned by -90 degrees, (v_y, -v_x)
 };
 
 // Stage description for the population passes.
