@@ -187,33 +187,109 @@ __device__ __forceinline__ cpx<T> ldc(twptr<T> p, int idx) {
     return cpx<T>{p[idx].re, p[idx].im};
 }
 
-// Twiddles w^q, q = 1..r-1, of base index `step` (w^q = tw[q*step]).  Radix 8 loads w, w^2, w^4
-// and forms the rest by at most two products; radix 4 loads w, w^2; radix 2, 3 load directly.
-template <typename T, int r, bool INV>
-__device__ __forceinline__ void twiddle_powers(twptr<T> tw, int step, cpx<T>* w) {
+// Number of twiddles a radix-r butterfly reads: radix 8 reads w, w^2, w^4 and forms the rest by at
+// most two products; radix 4 reads w, w^2; radix 2 and 3 read w^q, q = 1..r-1, directly.
+constexpr int tw_reads(int r) { return r == 8 ? 3 : (r == 4 ? 2 : r - 1); }
+
+// Twiddles w^q, q = 1..r-1, of one butterfly from its tw_reads(r) loaded values.
+template <typename T, int r>
+__device__ __forceinline__ void twiddle_powers(const cpx<T>* b, cpx<T>* w) {
     if constexpr (r == 8) {
-        w[1] = ldc(tw, step);
-        w[2] = ldc(tw, 2 * step);
-        w[4] = ldc(tw, 4 * step);
+        w[1] = b[0];
+        w[2] = b[1];
+        w[4] = b[2];
         w[3] = cmul(w[1], w[2]);
         w[5] = cmul(w[4], w[1]);
         w[6] = cmul(w[4], w[2]);
         w[7] = cmul(w[4], w[3]);
     } else if constexpr (r == 4) {
-        w[1] = ldc(tw, step);
-        w[2] = ldc(tw, 2 * step);
+        w[1] = b[0];
+        w[2] = b[1];
         w[3] = cmul(w[1], w[2]);
     } else {
 #pragma unroll
-        for (int q = 1; q < r; ++q) w[q] = ldc(tw, q * step);
+        for (int q = 1; q < r; ++q) w[q] = b[q - 1];
     }
 }
 
-// One Stockham pass of radix r with Ns = product of the previous radices.
+// The tw_reads(r) table values of a butterfly with base index `step`.
+template <typename T, int r>
+__device__ __forceinline__ void tw_fetch(twptr<T> table, int step, cpx<T>* d) {
+    if constexpr (r == 8) {
+        d[0] = ldc(table, step);
+        d[1] = ldc(table, 2 * step);
+        d[2] = ldc(table, 4 * step);
+    } else if constexpr (r == 4) {
+        d[0] = ldc(table, step);
+        d[1] = ldc(table, 2 * step);
+    } else {
+#pragma unroll
+        for (int q = 1; q < r; ++q) d[q - 1] = ldc(table, q * step);
+    }
+}
+
+// The twiddles one thread reads over all passes of a line transform (passes after the first).
+// Pass s with Ns = r_0...r_{s-1} gives butterfly b of thread t (element j = t + b*TPL,
+// k = j mod Ns) the powers of tw[k*N/(Ns*r)].  When they fit in a few registers (COUNT complex
+// values, at most LB_TW_PRELOAD) they are loaded together up front, so their latencies overlap,
+// and shared by the forward and inverse transforms of the line (the inverse multiplies by their
+// conjugates); otherwise each pass loads its own from the table.
+#ifndef LB_TW_PRELOAD
+#define LB_TW_PRELOAD 12
+#endif
+template <typename T, int N, int R>
+struct TwSet {
+    static constexpr Plan P = make_plan(N, R);
+    static constexpr int TPL = N / R;
+    static constexpr int offset(int s) {
+        int o = 0;
+        for (int i = 0; i < s; ++i)
+            if (plan_ns(P, i) > 1) o += (R / P.r[i]) * tw_reads(P.r[i]);
+        return o;
+    }
+    static constexpr int COUNT = offset(P.np);
+    static constexpr bool PRE = COUNT <= LB_TW_PRELOAD;
+    cpx<T> w[PRE && COUNT > 0 ? COUNT : 1];
+    twptr<T> table;
+    int t;
+
+    template <int s>
+    __device__ __forceinline__ void fetch(int b, cpx<T>* d) const {
+        constexpr int r = P.r[s], Ns = plan_ns(P, s);
+        tw_fetch<T, r>(table, ((t + b * TPL) % Ns) * (N / (Ns * r)), d);
+    }
+    template <int s>
+    __device__ __forceinline__ void load_pass() {
+        if constexpr (s < P.np) {
+            constexpr int r = P.r[s], Ns = plan_ns(P, s), NB = R / r, OFF = offset(s);
+            if constexpr (Ns > 1) {
+#pragma unroll
+                for (int b = 0; b < NB; ++b) fetch<s>(b, w + OFF + b * tw_reads(r));
+            }
+            load_pass<s + 1>();
+        }
+    }
+    __device__ __forceinline__ void load(twptr<T> tab, int thread) {
+        table = tab;
+        t = thread;
+        if constexpr (PRE) load_pass<0>();
+    }
+    // the preloaded tw_reads(r) values of butterfly b of pass s
+    template <int s>
+    __device__ __forceinline__ void get(int b, cpx<T>* d) const {
+        constexpr int r = P.r[s], OFF = offset(s);
+#pragma unroll
+        for (int i = 0; i < tw_reads(r); ++i) d[i] = w[OFF + b * tw_reads(r) + i];
+    }
+};
+
+// Pass S of the plan: one Stockham pass of radix r = P.r[S] with Ns = product of the previous radices.
 // LDS element i of the line lives at lds[lds_idx(i) * LS]: LS = 1 for line-contiguous storage,
 // LS = lines per block for lines interleaved word by word (lanes of neighbouring lines adjacent).
-template <typename T, int N, int R, int r, int Ns, bool INV, bool FROM_REG, bool TO_REG, int LS>
-__device__ __forceinline__ void stockham_pass(cpx<T> (&v)[R], cpx<T>* lds, int t, twptr<T> tw) {
+template <typename T, int N, int R, int S, bool INV, bool FROM_REG, bool TO_REG, int LS>
+__device__ __forceinline__ void stockham_pass(cpx<T> (&v)[R], cpx<T>* lds, int t, const TwSet<T, N, R>& tw) {
+    constexpr int r = TwSet<T, N, R>::P.r[S];
+    constexpr int Ns = plan_ns(TwSet<T, N, R>::P, S);
     constexpr int TPL = N / R;
     constexpr int NB = R / r;
     static_assert(R % r == 0, "radix must divide R");
@@ -236,8 +312,12 @@ __device__ __forceinline__ void stockham_pass(cpx<T> (&v)[R], cpx<T>* lds, int t
         const int j = t + b * TPL;
         const int k = j % Ns;
         if constexpr (Ns > 1) {
-            cpx<T> w[r];
-            twiddle_powers<T, r, INV>(tw, k * (N / (Ns * r)), w);
+            cpx<T> tb[tw_reads(r)], w[r];
+            if constexpr (TwSet<T, N, R>::PRE)
+                tw.template get<S>(b, tb);
+            else
+                tw_fetch<T, r>(tw.table, k * (N / (Ns * r)), tb);
+            twiddle_powers<T, r>(tb, w);
 #pragma unroll
             for (int q = 1; q < r; ++q) a[b * r + q] = INV ? cmulc(a[b * r + q], w[q]) : cmul(a[b * r + q], w[q]);
         }
@@ -259,24 +339,25 @@ template <typename T, int N, int R, bool INV, int LS = 1>
 struct LineFFT {
     static constexpr Plan P = make_plan(N, R);
     static constexpr int TPL = N / R;
+    using Tw = TwSet<T, N, R>;
 
     template <int s>
-    __device__ __forceinline__ static void passes(cpx<T> (&v)[R], cpx<T>* lds, int t, twptr<T> tw) {
+    __device__ __forceinline__ static void passes(cpx<T> (&v)[R], cpx<T>* lds, int t, const Tw& tw) {
         if constexpr (s < P.np) {
             constexpr int r = P.r[s];
-            constexpr int Ns = plan_ns(P, s);
             constexpr bool first = (s == 0);
             constexpr bool last = (s == P.np - 1);
             constexpr bool from_reg = first && (r == R);
             constexpr bool to_reg = last && (r == R);
-            stockham_pass<T, N, R, r, Ns, INV, from_reg, to_reg, LS>(v, lds, t, tw);
+            stockham_pass<T, N, R, s, INV, from_reg, to_reg, LS>(v, lds, t, tw);
             passes<s + 1>(v, lds, t, tw);
         }
     }
 
-    // Transform the line in place: v[m] = x[t + m*TPL] on entry, X[t + m*TPL] on exit.
-    // All threads of the workgroup must call this together (it contains barriers).
-    __device__ __forceinline__ static void run(cpx<T> (&v)[R], cpx<T>* lds, int t, twptr<T> tw) {
+    // Transform the line in place: v[m] = x[t + m*TPL] on entry, X[t + m*TPL] on exit, with the
+    // thread's twiddles already loaded.  All threads of the workgroup must call this together (it
+    // contains barriers).
+    __device__ __forceinline__ static void run(cpx<T> (&v)[R], cpx<T>* lds, int t, const Tw& tw) {
         if constexpr (P.np == 0) {
             return;
         } else {
@@ -295,6 +376,13 @@ struct LineFFT {
             // the next transform may write LDS that slower threads are still reading
             if constexpr (!(P.np == 1 && first_reg && last_reg)) __syncthreads();
         }
+    }
+
+    // The same, loading the twiddles from the table first.
+    __device__ __forceinline__ static void run(cpx<T> (&v)[R], cpx<T>* lds, int t, twptr<T> table) {
+        Tw tw;
+        tw.load(table, t);
+        run(v, lds, t, tw);
     }
 };
 

@@ -177,6 +177,31 @@ __device__ __forceinline__ void load_line(const LB_GLOBAL T* g, cpx<T> (&v)[R], 
     }
 }
 
+// The wavenumbers k[t + m*TPL] of a thread's R line elements: requested up front and kept in
+// registers for R <= 8; lines of 3 * 2^a points (R = 12) read them where they are used.
+#ifndef LB_WAVENUM_PRE
+#define LB_WAVENUM_PRE 8
+#endif
+template <typename T, int R, int TPL>
+struct Wavenum {
+    static constexpr bool PRE = R <= LB_WAVENUM_PRE;
+    T k[PRE ? R : 1];
+    const LB_GLOBAL T* kap;
+    int t;
+    __device__ __forceinline__ void load(const LB_GLOBAL T* table, int thread) {
+        kap = table;
+        t = thread;
+        if constexpr (PRE) {
+#pragma unroll
+            for (int m = 0; m < R; ++m) k[m] = kap[t + m * TPL];
+        }
+    }
+    __device__ __forceinline__ T operator[](int m) const {
+        if constexpr (PRE) return k[m];
+        else return kap[t + m * TPL];
+    }
+};
+
 // ---------------------------------------------------------------------------------------
 // Macroscopic line pass driven by a job table.
 template <typename T, int N, int DIR>
@@ -207,7 +232,12 @@ macro_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
 
     cpx<T> X[R], Y[R];
     load_line<T, DIR, R, TPL>(fieldp<T>(I, J.in), X, line, t, nx, ny, active);
-    FFT::run(X, lds, t, tw);
+    // twiddles and wavenumbers are shared by the forward and both inverse transforms
+    typename FFT::Tw tws;
+    tws.load(tw, t);
+    Wavenum<T, R, TPL> kv;
+    kv.load(kap, t);
+    FFT::run(X, lds, t, tws);
     const T invN = T(1.0 / N);
 #pragma unroll 1
     for (int o = 0; o < 2; ++o) {
@@ -216,8 +246,8 @@ macro_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
         if (outf < 0) continue;
         const int mk = o == 0 ? J.mult[0] : J.mult[1];
 #pragma unroll
-        for (int m = 0; m < R; ++m) Y[m] = spectral_mult<T>(mk, kap[t + m * TPL], invN, X[m]);
-        IFFT::run(Y, lds, t, tw);
+        for (int m = 0; m < R; ++m) Y[m] = spectral_mult<T>(mk, kv[m], invN, X[m]);
+        IFFT::run(Y, lds, t, tws);
         if (!active) continue;
         LB_GLOBAL T* out = fieldp<T>(I, outf);
 #pragma unroll
@@ -431,20 +461,25 @@ pop_x_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
     for (int q = 0; q < P; ++q)
         load_line<T, 0, R, TPL>(fieldp<T>(I, st.f_field + D.xorder[w.job * P + q]), X[q], line, t,
                                 nx, ny, active);
+    // twiddles and wavenumbers are shared by the block's 2P transforms
+    typename LineFFT<T, N, R, false>::Tw tws;
+    tws.load(tw, t);
+    Wavenum<T, R, TPL> kv;
+    kv.load(kap, t);
 #pragma unroll
     for (int q = 0; q < P; ++q) {
         const int i = D.xorder[w.job * P + q];
         const T vx = D.vx[i];
         if (vx != T(0)) {
-            LineFFT<T, N, R, false>::run(X[q], lds, t, tw);
+            LineFFT<T, N, R, false>::run(X[q], lds, t, tws);
             const T s = -c * vx * invN, mr = -ct * invN;
 #pragma unroll
             for (int m = 0; m < R; ++m) {
-                const T mi = s * kap[t + m * TPL];
+                const T mi = s * kv[m];
                 const cpx<T> x = X[q][m];
                 X[q][m] = {mr * x.re - mi * x.im, mr * x.im + mi * x.re};
             }
-            LineFFT<T, N, R, true>::run(X[q], lds, t, tw);
+            LineFFT<T, N, R, true>::run(X[q], lds, t, tws);
         } else {
 #pragma unroll
             for (int m = 0; m < R; ++m) X[q][m] = {-ct * X[q][m].re, -ct * X[q][m].im};
@@ -497,30 +532,34 @@ pop_y_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
     const T vy = dvm->vy[i];
     const twptr<T> tw = gcast(reinterpret_cast<const cpx<T>*>(I.twy));
 
+    // the line, the partial sums it is added to, the twiddles and the wavenumbers are all
+    // requested before the transforms so that their latencies overlap
     cpx<T> X[R];
     load_line<T, 1, R, TPL>(fieldp<T>(I, st.f_field + i), X, line, t, nx, ny, active);
-    LineFFT<T, N, R, false, C::LS>::run(X, lds, t, tw);
+    cpx<T> Pv[R];
+    load_line<T, 1, R, TPL>(fieldp<T>(I, F_P + i), Pv, line, t, nx, ny, active);
+    typename LineFFT<T, N, R, false, C::LS>::Tw tws;
+    tws.load(tw, t);
     const LB_GLOBAL T* kap = gcast(reinterpret_cast<const T*>(I.ky));
+    Wavenum<T, R, TPL> kv;
+    kv.load(kap, t);
+    LineFFT<T, N, R, false, C::LS>::run(X, lds, t, tws);
     const T s = -T(st.use_dt ? st.alpha * I.dt : st.alpha) * vy * T(1.0 / N);
 #pragma unroll
     for (int m = 0; m < R; ++m) {
-        const T a = s * kap[t + m * TPL];
+        const T a = s * kv[m];
         const cpx<T> x = X[m];
         X[m] = {-a * x.im, a * x.re};
     }
-    LineFFT<T, N, R, true, C::LS>::run(X, lds, t, tw);
+    LineFFT<T, N, R, true, C::LS>::run(X, lds, t, tws);
     if (!active) return;
-    const LB_GLOBAL T* part = fieldp<T>(I, F_P + i);
     LB_GLOBAL T* out = fieldp<T>(I, st.out_field + i);
 #pragma unroll
     for (int m = 0; m < R; ++m) {
         const int p = t + m * TPL;
-        const uint32_t e = LineAddr<1>::re(line, p, nx);
-        const LB_GLOBAL vec2<T>* pv = reinterpret_cast<const LB_GLOBAL vec2<T>*>(part + e);
-        const T a = pv->a + X[m].re, b = pv->b + X[m].im;
-        LB_GLOBAL vec2<T>* o = reinterpret_cast<LB_GLOBAL vec2<T>*>(out + e);
-        o->a = a;
-        o->b = b;
+        LB_GLOBAL vec2<T>* o = reinterpret_cast<LB_GLOBAL vec2<T>*>(out + LineAddr<1>::re(line, p, nx));
+        o->a = Pv[m].re + X[m].re;
+        o->b = Pv[m].im + X[m].im;
     }
 }
 
