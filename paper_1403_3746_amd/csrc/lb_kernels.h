@@ -532,12 +532,14 @@ pop_y_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
     const T vy = dvm->vy[i];
     const twptr<T> tw = gcast(reinterpret_cast<const cpx<T>*>(I.twy));
 
-    // the line, the partial sums it is added to, the twiddles and the wavenumbers are all
-    // requested before the transforms so that their latencies overlap
+    // the line, the twiddles and the wavenumbers (and in FP32 the partial sums the result is
+    // added to) are requested before the transforms so that their latencies overlap; in FP64 the
+    // partial sums are read after the transforms, all before the first store, to spare registers
+    constexpr bool EARLY = sizeof(T) == 4;
     cpx<T> X[R];
     load_line<T, 1, R, TPL>(fieldp<T>(I, st.f_field + i), X, line, t, nx, ny, active);
     cpx<T> Pv[R];
-    load_line<T, 1, R, TPL>(fieldp<T>(I, F_P + i), Pv, line, t, nx, ny, active);
+    if constexpr (EARLY) load_line<T, 1, R, TPL>(fieldp<T>(I, F_P + i), Pv, line, t, nx, ny, active);
     typename LineFFT<T, N, R, false, C::LS>::Tw tws;
     tws.load(tw, t);
     const LB_GLOBAL T* kap = gcast(reinterpret_cast<const T*>(I.ky));
@@ -553,6 +555,7 @@ pop_y_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
     }
     LineFFT<T, N, R, true, C::LS>::run(X, lds, t, tws);
     if (!active) return;
+    if constexpr (!EARLY) load_line<T, 1, R, TPL>(fieldp<T>(I, F_P + i), Pv, line, t, nx, ny, true);
     LB_GLOBAL T* out = fieldp<T>(I, st.out_field + i);
 #pragma unroll
     for (int m = 0; m < R; ++m) {
