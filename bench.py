@@ -42,6 +42,9 @@ ALG_WORDS = {
     "pop_y": 36,       # read 12 f + 12 partials; write 12
 }
 WORDS_PER_STEP = 2 * sum(ALG_WORDS.values())   # 328
+# On square grids the x and y macroscopic passes of a stage run as one fused launch, timed in the
+# x slot: its algorithmic words are those of both.
+FUSED = {"macro_x1": ("macro_xy1", "macro_y1"), "macro_x2": ("macro_xy2", "macro_y2")}
 
 
 def kernel_source_hash():
@@ -95,11 +98,15 @@ def run_gpu(instances, precision, steps, warmup, timed_steps):
 
 def roofline(res, word_bytes, workload):
     cells = res["cells"]
+    passes = res["passes"]
     per_pass = {}
-    for name, ms in res["passes"].items():
+    for name, ms in passes.items():
         if ms <= 0:
             continue
-        alg = ALG_WORDS[name] * word_bytes * cells
+        words = ALG_WORDS[name]
+        if name in FUSED and passes.get(FUSED[name][1], 0.0) <= 0:
+            name, words = FUSED[name][0], words + ALG_WORDS[FUSED[name][1]]
+        alg = words * word_bytes * cells
         per_pass[name] = dict(ms=ms, alg_bytes=alg, gbs=alg / (ms * 1e-3) / 1e9)
     dom = max(per_pass, key=lambda k: per_pass[k]["ms"])
     d = per_pass[dom]

@@ -335,6 +335,72 @@ __device__ __forceinline__ void stockham_pass(cpx<T> (&v)[R], cpx<T>* lds, int t
     if constexpr (!TO_REG) __syncthreads();
 }
 
+// Pass S for Q lines at once (line q's LDS region starts `stride` complex words after line
+// q-1's): one LDS round trip and one pair of barriers for all Q lines, the butterflies' twiddle
+// powers formed once and applied to every line, and Q independent butterflies per twiddle set for
+// the scheduler to interleave.
+template <typename T, int N, int R, int S, bool INV, bool FROM_REG, bool TO_REG, int LS, int Q>
+__device__ __forceinline__ void stockham_pass_n(cpx<T> (&v)[Q][R], cpx<T>* lds, int stride, int t,
+                                                const TwSet<T, N, R>& tw) {
+    constexpr int r = TwSet<T, N, R>::P.r[S];
+    constexpr int Ns = plan_ns(TwSet<T, N, R>::P, S);
+    constexpr int TPL = N / R;
+    constexpr int NB = R / r;
+    static_assert(R % r == 0, "radix must divide R");
+    cpx<T> a[Q][R];
+    if constexpr (FROM_REG) {
+        static_assert(NB == 1, "register-direct pass needs r == R");
+#pragma unroll
+        for (int l = 0; l < Q; ++l)
+#pragma unroll
+            for (int q = 0; q < r; ++q) a[l][q] = v[l][q];
+    } else {
+#pragma unroll
+        for (int l = 0; l < Q; ++l)
+#pragma unroll
+            for (int b = 0; b < NB; ++b) {
+                const int j = t + b * TPL;
+#pragma unroll
+                for (int q = 0; q < r; ++q) a[l][b * r + q] = lds[l * stride + lds_idx(j + q * (N / r)) * LS];
+            }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int b = 0; b < NB; ++b) {
+        const int j = t + b * TPL;
+        const int k = j % Ns;
+        if constexpr (Ns > 1) {
+            cpx<T> tb[tw_reads(r)], w[r];
+            if constexpr (TwSet<T, N, R>::PRE)
+                tw.template get<S>(b, tb);
+            else
+                tw_fetch<T, r>(tw.table, k * (N / (Ns * r)), tb);
+            twiddle_powers<T, r>(tb, w);
+#pragma unroll
+            for (int l = 0; l < Q; ++l)
+#pragma unroll
+                for (int q = 1; q < r; ++q)
+                    a[l][b * r + q] = INV ? cmulc(a[l][b * r + q], w[q]) : cmul(a[l][b * r + q], w[q]);
+        }
+#pragma unroll
+        for (int l = 0; l < Q; ++l) Dft<T, r, INV>::run(&a[l][b * r]);
+        if constexpr (TO_REG) {
+            static_assert(NB == 1, "register-direct pass needs r == R");
+#pragma unroll
+            for (int l = 0; l < Q; ++l)
+#pragma unroll
+                for (int q = 0; q < r; ++q) v[l][q] = a[l][q];
+        } else {
+            const int base = (j / Ns) * Ns * r + k;
+#pragma unroll
+            for (int l = 0; l < Q; ++l)
+#pragma unroll
+                for (int q = 0; q < r; ++q) lds[l * stride + lds_idx(base + q * Ns) * LS] = a[l][b * r + q];
+        }
+    }
+    if constexpr (!TO_REG) __syncthreads();
+}
+
 template <typename T, int N, int R, bool INV, int LS = 1>
 struct LineFFT {
     static constexpr Plan P = make_plan(N, R);
@@ -374,6 +440,45 @@ struct LineFFT {
                 for (int m = 0; m < R; ++m) v[m] = lds[lds_idx(t + m * TPL) * LS];
             }
             // the next transform may write LDS that slower threads are still reading
+            if constexpr (!(P.np == 1 && first_reg && last_reg)) __syncthreads();
+        }
+    }
+
+    template <int s, int Q>
+    __device__ __forceinline__ static void passes_n(cpx<T> (&v)[Q][R], cpx<T>* lds, int stride, int t,
+                                                    const Tw& tw) {
+        if constexpr (s < P.np) {
+            constexpr int r = P.r[s];
+            constexpr bool from_reg = (s == 0) && (r == R);
+            constexpr bool to_reg = (s == P.np - 1) && (r == R);
+            stockham_pass_n<T, N, R, s, INV, from_reg, to_reg, LS, Q>(v, lds, stride, t, tw);
+            passes_n<s + 1, Q>(v, lds, stride, t, tw);
+        }
+    }
+
+    // Transform Q lines together (line l's LDS region at lds + l*stride); same contract as run.
+    template <int Q>
+    __device__ __forceinline__ static void run_n(cpx<T> (&v)[Q][R], cpx<T>* lds, int stride, int t,
+                                                 const Tw& tw) {
+        if constexpr (P.np == 0) {
+            return;
+        } else {
+            constexpr bool first_reg = (P.r[0] == R);
+            constexpr bool last_reg = (P.r[P.np - 1] == R);
+            if constexpr (!first_reg) {
+#pragma unroll
+                for (int l = 0; l < Q; ++l)
+#pragma unroll
+                    for (int m = 0; m < R; ++m) lds[l * stride + lds_idx(t + m * TPL) * LS] = v[l][m];
+                __syncthreads();
+            }
+            passes_n<0, Q>(v, lds, stride, t, tw);
+            if constexpr (!last_reg) {
+#pragma unroll
+                for (int l = 0; l < Q; ++l)
+#pragma unroll
+                    for (int m = 0; m < R; ++m) v[l][m] = lds[l * stride + lds_idx(t + m * TPL) * LS];
+            }
             if constexpr (!(P.np == 1 && first_reg && last_reg)) __syncthreads();
         }
     }

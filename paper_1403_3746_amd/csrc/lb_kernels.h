@@ -27,6 +27,9 @@
 #ifndef LB_POPX_WAVES
 #define LB_POPX_WAVES 4  // waves per SIMD the single-population FP32 x pass must fit (register budget)
 #endif
+#ifndef LB_POPX_BATCH_LDS
+#define LB_POPX_BATCH_LDS 40960  // LDS bytes up to which the x pass transforms its P lines together
+#endif
 #ifndef LB_POPX_WAVES_F64
 #define LB_POPX_WAVES_F64 3  // the same for FP64 (fewer: its epilogue holds twice the registers)
 #endif
@@ -39,7 +42,7 @@ namespace lbfft {
 // on the same XCD (see decode_block) so partially used cache lines are reused from L2.
 // LDS: x blocks (lanes of one line adjacent) store each line contiguously; y blocks (lanes of
 // neighbouring lines adjacent) interleave their lines word by word (LS = LPW).
-template <typename T, int N, int DIR>
+template <typename T, int N, int DIR, int LPW_OVERRIDE = 0>
 struct LineCfg {
     static constexpr int R = default_R(N);
     static constexpr int TPL = N / R;
@@ -52,7 +55,7 @@ struct LineCfg {
         int l = at_least(at_least(LB_YSEG / CB, 64 / TPL), 1);
         return (l * TPL > 512) ? at_least(512 / TPL, 1) : l;
     }
-    static constexpr int LPW = DIR == 0 ? lpw_x() : lpw_y();
+    static constexpr int LPW = LPW_OVERRIDE > 0 ? LPW_OVERRIDE : (DIR == 0 ? lpw_x() : lpw_y());
     static constexpr int WG = LPW * TPL;
     static constexpr int LS = DIR == 0 ? 1 : LPW;
     static constexpr int LDS = LPW * lds_line(N);   // complex words
@@ -71,8 +74,7 @@ struct BlockWork {
 
 __host__ __device__ constexpr int groups_per_xcd(int ngroups) { return (ngroups + 7) / 8; }
 
-__device__ __forceinline__ BlockWork decode_block(int ngroups, int ntiles, int njobs) {
-    const int b = blockIdx.x;
+__device__ __forceinline__ BlockWork decode_block_at(int b, int ngroups, int ntiles, int njobs) {
     const int xcd = b & 7;
     const int slot = b >> 3;
     const int gpx = groups_per_xcd(ngroups);
@@ -84,6 +86,10 @@ __device__ __forceinline__ BlockWork decode_block(int ngroups, int ntiles, int n
     w.inst_local = group / ntiles;
     w.tile = group % ntiles;
     return w;
+}
+
+__device__ __forceinline__ BlockWork decode_block(int ngroups, int ntiles, int njobs) {
+    return decode_block_at(blockIdx.x, ngroups, ntiles, njobs);
 }
 
 // Spectral multiplier kind mk applied to coefficient x of wavenumber k, including the 1/N of the
@@ -203,17 +209,17 @@ struct Wavenum {
 };
 
 // ---------------------------------------------------------------------------------------
-// Macroscopic line pass driven by a job table.
-template <typename T, int N, int DIR>
-__global__ void __launch_bounds__((LineCfg<T, N, DIR>::WG))
-macro_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, int ngroups,
-           int ntiles, const JobDesc* __restrict__ jobs, int njobs) {
-    using C = LineCfg<T, N, DIR>;
+// Macroscopic line pass driven by a job table: the work of block b (LPW lines per block).
+template <typename T, int N, int DIR, int LPW_>
+__device__ __forceinline__ void macro_body(int b, const InstDesc* __restrict__ insts,
+                                           const int* __restrict__ ilist, int ngroups, int ntiles,
+                                           const JobDesc* __restrict__ jobs, int njobs,
+                                           cpx<T>* lds_all) {
+    using C = LineCfg<T, N, DIR, LPW_>;
     using FFT = LineFFT<T, N, C::R, false, C::LS>;
     using IFFT = LineFFT<T, N, C::R, true, C::LS>;
     constexpr int R = C::R, TPL = C::TPL, LPW = C::LPW;
-    __shared__ cpx<T> lds_all[C::LDS];
-    const BlockWork w = decode_block(ngroups, ntiles, njobs);
+    const BlockWork w = decode_block_at(b, ngroups, ntiles, njobs);
     if (!w.valid) return;
     const InstDesc& I = insts[ilist[w.inst_local]];
     const JobDesc J = jobs[w.job];
@@ -263,6 +269,40 @@ macro_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
             }
         }
     }
+}
+
+template <typename T, int N, int DIR>
+__global__ void __launch_bounds__((LineCfg<T, N, DIR>::WG))
+macro_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, int ngroups,
+           int ntiles, const JobDesc* __restrict__ jobs, int njobs) {
+    using C = LineCfg<T, N, DIR>;
+    __shared__ cpx<T> lds_all[C::LDS];
+    macro_body<T, N, DIR, C::LPW>(blockIdx.x, insts, ilist, ngroups, ntiles, jobs, njobs, lds_all);
+}
+
+// The x and y macroscopic passes of one stage of a square grid in one launch: the two read the
+// same moments and write different fields, so their blocks can run side by side.  Blocks below
+// nbx take x tiles, the rest y tiles; both use the y pass's block shape (x tiles of as many lines).
+template <typename T, int N>
+struct MacroXY {
+    static constexpr int LPW = LineCfg<T, N, 1>::LPW;
+    static constexpr int WG = LineCfg<T, N, 1>::WG;
+    static constexpr int LDS = LineCfg<T, N, 1>::LDS;
+    static_assert(LineCfg<T, N, 0, LPW>::WG == WG && LineCfg<T, N, 0, LPW>::LDS == LDS,
+                  "x and y tiles of the fused pass must have one block shape");
+};
+
+template <typename T, int N>
+__global__ void __launch_bounds__((MacroXY<T, N>::WG))
+macro_xy_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, int nbx,
+              int ngroups_x, int ntiles_x, const JobDesc* __restrict__ jobs_x, int njobs_x,
+              int ngroups_y, int ntiles_y, const JobDesc* __restrict__ jobs_y, int njobs_y) {
+    __shared__ cpx<T> lds_all[MacroXY<T, N>::LDS];
+    const int b = blockIdx.x;
+    if (b < nbx)
+        macro_body<T, N, 0, MacroXY<T, N>::LPW>(b, insts, ilist, ngroups_x, ntiles_x, jobs_x, njobs_x, lds_all);
+    else
+        macro_body<T, N, 1, MacroXY<T, N>::LPW>(b - nbx, insts, ilist, ngroups_y, ntiles_y, jobs_y, njobs_y, lds_all);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -436,7 +476,9 @@ pop_x_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
            int ntiles, const DvmConst<T>* __restrict__ dvm, StageArgs st) {
     using C = LineCfg<T, N, 0>;
     constexpr int R = C::R, TPL = C::TPL;
-    __shared__ cpx<T> lds_all[C::LDS];
+    // the block's P lines are transformed together when their LDS fits the budget
+    constexpr bool BATCH = P > 1 && P * C::LDS * (int)sizeof(cpx<T>) <= LB_POPX_BATCH_LDS;
+    __shared__ cpx<T> lds_all[BATCH ? P * C::LDS : C::LDS];
     const BlockWork w = decode_block(ngroups, ntiles, 16 / P);
     if (!w.valid) return;
     const InstDesc& I = insts[ilist[w.inst_local]];
@@ -466,8 +508,31 @@ pop_x_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
     tws.load(tw, t);
     Wavenum<T, R, TPL> kv;
     kv.load(kap, t);
+    if constexpr (BATCH) {
+        // the block's populations all have v_x != 0 or all v_x = 0 (pairs in x-pass order)
+        const T vx0 = D.vx[D.xorder[w.job * P]];
+        if (vx0 != T(0)) {
+            LineFFT<T, N, R, false>::template run_n<P>(X, lds, C::LDS, t, tws);
 #pragma unroll
-    for (int q = 0; q < P; ++q) {
+            for (int q = 0; q < P; ++q) {
+                const T s = -c * D.vx[D.xorder[w.job * P + q]] * invN, mr = -ct * invN;
+#pragma unroll
+                for (int m = 0; m < R; ++m) {
+                    const T mi = s * kv[m];
+                    const cpx<T> x = X[q][m];
+                    X[q][m] = {mr * x.re - mi * x.im, mr * x.im + mi * x.re};
+                }
+            }
+            LineFFT<T, N, R, true>::template run_n<P>(X, lds, C::LDS, t, tws);
+        } else {
+#pragma unroll
+            for (int q = 0; q < P; ++q)
+#pragma unroll
+                for (int m = 0; m < R; ++m) X[q][m] = {-ct * X[q][m].re, -ct * X[q][m].im};
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < (BATCH ? 0 : P); ++q) {
         const int i = D.xorder[w.job * P + q];
         const T vx = D.vx[i];
         if (vx != T(0)) {

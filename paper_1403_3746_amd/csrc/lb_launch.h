@@ -40,6 +40,10 @@ hipError_t pop_y_f64(const LaunchSet& L, const DvmConst<double>* dvm, const int*
 hipError_t pop_x_f32(const LaunchSet& L, const DvmConst<float>* dvm, const int* pops, int npops, StageArgs st);
 hipError_t pop_y_f32(const LaunchSet& L, const DvmConst<float>* dvm, const int* pops, int npops, StageArgs st);
 
+// Fused x + y macroscopic passes of square grids (lb_lines_xy_<prec>.hip).
+hipError_t macro_xy_f64(const LaunchSet& L, const JobDesc* jx, int njx, const JobDesc* jy, int njy);
+hipError_t macro_xy_f32(const LaunchSet& L, const JobDesc* jx, int njx, const JobDesc* jy, int njy);
+
 // Pointwise kernels (lb_pointwise.hip).
 template <typename T>
 hipError_t launch_moments(const LaunchSet& L, const DvmConst<T>* dvm, int f_field);

@@ -183,6 +183,7 @@ struct lb_ctx {
     hipGraphExec_t exec = nullptr;
     bool use_graph = true;
     int ppb_override = 0;   // populations per x-pass block forced by LBFFT_PPB (1, 2 or 4), else tuned
+    bool fuse_xy = true;    // square grids: x and y macroscopic passes in one launch (LBFFT_FUSE_XY=0: off)
 
     template <typename Q>
     Q* dev(size_t off) const { return reinterpret_cast<Q*>(ws + off); }
@@ -260,6 +261,14 @@ LaunchSet set_one(const lb_ctx& c, int inst, hipStream_t s) {
     return L;
 }
 
+// The x and y macroscopic passes of a square grid run as one fused launch, issued in the x slot.
+bool fused_xy(const lb_ctx& c, const LaunchSet& L) { return c.fuse_xy && L.nx == L.ny; }
+
+hipError_t macro_xy(const lb_ctx& c, const LaunchSet& L, int jx, int njx, int jy, int njy) {
+    if (c.prec == LB_FP64) return macro_xy_f64(L, c.d_jobs(jx), njx, c.d_jobs(jy), njy);
+    return macro_xy_f32(L, c.d_jobs(jx), njx, c.d_jobs(jy), njy);
+}
+
 hipError_t macro(const lb_ctx& c, const LaunchSet& L, int dir, int j0, int nj) {
     const JobDesc* jt = c.d_jobs(j0);
     if (c.prec == LB_FP64) return dir == 0 ? macro_x_f64(L, jt, nj) : macro_y_f64(L, jt, nj);
@@ -302,11 +311,19 @@ hipError_t pop_y(const lb_ctx& c, const LaunchSet& L, StageArgs st) {
 hipError_t run_pass(const lb_ctx& c, const LaunchSet& L, int kind, StageArgs st) {
     switch (kind) {
         case LB_PASS_MOMENTS: return moments(c, L, st.f_field);
-        case LB_PASS_MACRO_X1: return macro(c, L, 0, c.j_x1, c.n_x1);
-        case LB_PASS_MACRO_Y1: return macro(c, L, 1, c.j_y1, c.n_y1);
+        case LB_PASS_MACRO_X1:
+            if (fused_xy(c, L)) return macro_xy(c, L, c.j_x1, c.n_x1, c.j_y1, c.n_y1);
+            return macro(c, L, 0, c.j_x1, c.n_x1);
+        case LB_PASS_MACRO_Y1:
+            if (fused_xy(c, L)) return hipSuccess;   // done by the fused launch in the x slot
+            return macro(c, L, 1, c.j_y1, c.n_y1);
         case LB_PASS_STRESS: return stress(c, L);
-        case LB_PASS_MACRO_X2: return macro(c, L, 0, c.j_x2, c.n_x2);
-        case LB_PASS_MACRO_Y2: return macro(c, L, 1, c.j_y2, c.n_y2);
+        case LB_PASS_MACRO_X2:
+            if (fused_xy(c, L)) return macro_xy(c, L, c.j_x2, c.n_x2, c.j_y2, c.n_y2);
+            return macro(c, L, 0, c.j_x2, c.n_x2);
+        case LB_PASS_MACRO_Y2:
+            if (fused_xy(c, L)) return hipSuccess;
+            return macro(c, L, 1, c.j_y2, c.n_y2);
         case LB_PASS_FINALIZE: return finalize(c, L);
         case LB_PASS_POP_X: return pop_x(c, L, st);
         case LB_PASS_POP_Y: return pop_y(c, L, st);
@@ -334,13 +351,15 @@ hipError_t launch_pass(const lb_ctx& c, const lb_ctx::Class& cl, hipStream_t s, 
                        StageArgs st, PassHook* hook) {
     LaunchSet L = set_of(c, cl);
     L.stream = s;
+    // a y pass fused into its x launch launches nothing (and takes no timing events)
+    if ((k == LB_PASS_MACRO_Y1 || k == LB_PASS_MACRO_Y2) && fused_xy(c, L)) return hipSuccess;
     if (hook && !hook->events(k, &L.ev_start, &L.ev_stop)) return hipErrorInvalidValue;
     return run_pass(c, L, k, st);
 }
 
 // One Runge-Kutta stage of the instances of one size class on stream s:
 //   moments -> X1 -> Y1 -> stress -> X2 -> Y2 -> finalize -> pop x -> pop y.
-// (X1/Y1 and X2/Y2 are independent; they are issued in order on one stream.)
+// (X1/Y1 and X2/Y2 are independent: one fused launch each on square grids, else in order.)
 hipError_t enqueue_class_stage(const lb_ctx& c, const lb_ctx::Class& cl, hipStream_t s,
                                StageArgs st, PassHook* hook) {
     for (int k = 0; k < LB_NPASS; ++k) {
@@ -537,6 +556,7 @@ lb_status lb_init(lb_ctx** out, int n_inst, const lb_params* p, const lb_dvm* dv
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
     c->lay = lay;
     if (const char* g = std::getenv("LBFFT_NO_GRAPH")) c->use_graph = !(g[0] == '1');
+    if (const char* g = std::getenv("LBFFT_FUSE_XY")) c->fuse_xy = !(g[0] == '0');
     if (const char* g = std::getenv("LBFFT_PPB")) {
         const int v = std::atoi(g);
         if (v == 1 || v == 2 || v == 4) c->ppb_override = v;

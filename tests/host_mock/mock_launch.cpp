@@ -1,12 +1,13 @@
 // No-op stand-ins for the kernel launch functions, with argument checks (CPU check of the host
 // runtime).
-// No-op launch functions with argument checks, standing in for the kernel units.
 #include "lb_launch.h"
 #include <cassert>
 namespace lbfft {
 static void chk(const LaunchSet& L) { assert(L.insts && L.ilist && L.ninst > 0 && L.nx > 0 && L.ny > 0); }
 #define M(name, T) hipError_t name(const LaunchSet& L, const JobDesc* j, int n) { chk(L); assert(j && n > 0); return hipSuccess; }
 M(macro_x_f64, double) M(macro_y_f64, double) M(macro_x_f32, float) M(macro_y_f32, float)
+#define MXY(name) hipError_t name(const LaunchSet& L, const JobDesc* a, int na, const JobDesc* b, int nb) { chk(L); assert(L.nx == L.ny && a && b && na > 0 && nb > 0); return hipSuccess; }
+MXY(macro_xy_f64) MXY(macro_xy_f32)
 #define P(name, T) hipError_t name(const LaunchSet& L, const DvmConst<T>* d, const int* p, int n, StageArgs) { chk(L); assert(d && p); return hipSuccess; }
 P(pop_x_f64, double) P(pop_y_f64, double) P(pop_x_f32, float) P(pop_y_f32, float)
 template <typename T> hipError_t launch_moments(const LaunchSet& L, const DvmConst<T>*, int) { chk(L); return hipSuccess; }

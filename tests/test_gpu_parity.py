@@ -218,6 +218,26 @@ def test_step_timed_matches_graph_step(torch_cuda):
     b.close()
 
 
+def test_fused_xy_passes_match_separate_passes(torch_cuda, monkeypatch):
+    # square grids run the x and y macroscopic passes of a stage as one launch; the per-line
+    # arithmetic is the same, so the state must agree bit for bit with the separate launches
+    p = W.base_params()
+    ic = W.quench(96, 96, 0.52, 21)
+    monkeypatch.setenv("LBFFT_PPB", "2")   # same x-pass plan for both (no tuning difference)
+    for prec in ("fp64", "fp32"):
+        monkeypatch.setenv("LBFFT_FUSE_XY", "0")
+        sep = _sim([(p, ic)], prec)
+        monkeypatch.delenv("LBFFT_FUSE_XY")
+        fused = _sim([(p, ic)], prec)
+        sep.step(5)
+        ms = fused.step_timed(5)
+        assert ms["macro_y1"] == 0 and ms["macro_y2"] == 0, ms
+        assert all(ms[k] > 0 for k in ms if k not in ("macro_y1", "macro_y2")), ms
+        assert np.array_equal(sep.get_f(), fused.get_f()), prec
+        sep.close()
+        fused.close()
+
+
 def test_conservation_history_matches_oracle(torch_cuda):
     p = W.base_params(q=-0.004, hist=20)
     ic = W.smooth_random(48, 32, 17, T0=0.5)
