@@ -373,8 +373,11 @@ __device__ __forceinline__ T feq_pop(const DvmConst<T>& D, int i, T rho, T ux, T
 // u_y, T, B_x, B_y, C) and the P base values, and writes P results.  The cells run in groups of
 // LB_EPI_CELLS_F64 / _F32 whose reads are issued one group ahead of the group being computed and stored, so a
 // thread has the next group's loads in flight instead of waiting on each cell's loads in turn.
+#ifndef LB_EPI_FENCE
+#define LB_EPI_FENCE 1
+#endif
 #ifndef LB_EPI_CELLS_F64
-#define LB_EPI_CELLS_F64 1
+#define LB_EPI_CELLS_F64 2
 #endif
 #ifndef LB_EPI_CELLS_F32
 #define LB_EPI_CELLS_F32 4
@@ -551,8 +554,10 @@ pop_x_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
         }
     }
     if (!active) return;
+#if LB_EPI_FENCE
     // keep the epilogue's loads out of the transforms above (their registers would be live there)
     asm volatile("" ::: "memory");
+#endif
     int pop[P];
 #pragma unroll
     for (int q = 0; q < P; ++q) pop[q] = D.xorder[w.job * P + q];
