@@ -49,7 +49,7 @@ FUSED = {"macro_x1": ("macro_xy1", "macro_y1"), "macro_x2": ("macro_xy2", "macro
 
 def kernel_source_hash():
     h = hashlib.sha256()
-    for f in ("lb_kernels.h", "lb_fft.h", "lb_lines.inc"):
+    for f in ("lb_kernels.h", "lb_fft.h", "lb_lines.inc", "lb_lines_xy.inc", "lb_pointwise.hip"):
         h.update(open(os.path.join(ROOT, "paper_1403_3746_amd", "csrc", f), "rb").read())
     return h.hexdigest()[:16]
 
