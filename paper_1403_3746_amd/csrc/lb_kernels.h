@@ -373,6 +373,9 @@ __device__ __forceinline__ T feq_pop(const DvmConst<T>& D, int i, T rho, T ux, T
 // u_y, T, B_x, B_y, C) and the P base values, and writes P results.  The cells run in groups of
 // LB_EPI_CELLS_F64 / _F32 whose reads are issued one group ahead of the group being computed and stored, so a
 // thread has the next group's loads in flight instead of waiting on each cell's loads in turn.
+#ifndef LB_EPI_EARLY_F64
+#define LB_EPI_EARLY_F64 1
+#endif
 #ifndef LB_EPI_FENCE
 #define LB_EPI_FENCE 1
 #endif
@@ -415,10 +418,9 @@ struct PopXEpi {
         }
     }
     // rotu: the block's pairs are y mirrors (v_x = 0); their equilibria are those of the x-mirror
-    // pairs rot(i) at the turned velocity (u_y, -u_x)
-    __device__ __forceinline__ void run(const cpx<T> (&X)[P][R], bool rotu) const {
-        T v[2][G][NV];
-        load(0, v[0]);
+    // pairs rot(i) at the turned velocity (u_y, -u_x).  v[0] holds the first group's inputs
+    // (requested by the caller with load(0, v[0]), possibly before the transforms).
+    __device__ __forceinline__ void run(const cpx<T> (&X)[P][R], bool rotu, T (&v)[2][G][NV]) const {
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
             if (g + 1 < NG) load(g + 1, v[(g + 1) & 1]);
@@ -499,6 +501,31 @@ pop_x_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
     const LB_GLOBAL T* kap = gcast(reinterpret_cast<const T*>(I.kx));
     const T invN = T(1.0 / N);
 
+    int pop[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) pop[q] = D.xorder[w.job * P + q];
+    const bool has_base = st.base_field >= 0;
+    const uint32_t cf[7] = {fofs<T>(I, RHO), fofs<T>(I, UX), fofs<T>(I, UY), fofs<T>(I, TT),
+                            fofs<T>(I, BX), fofs<T>(I, BY), fofs<T>(I, CT)};
+    uint32_t basep[P], outp[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) {
+        // without a base (the bare right-hand side) the partial block is read and discarded
+        basep[q] = fofs<T>(I, has_base ? st.base_field + pop[q] : F_P + pop[q]);
+        // out may equal the base block (second stage writes f^{n+1} over f^n per cell)
+        outp[q] = fofs<T>(I, (D.vy[pop[q]] == T(0) ? st.out_field : F_P) + pop[q]);
+    }
+    const bool row1 = 2 * line + 1 < ny;
+    const PopXEpi<T, R, TPL, P> epi{D, pop, arena<T>(I), cf, basep, outp, has_base, line, t, nx, row1,
+                                    T(I.b), c, inv_tau};
+    using Epi = PopXEpi<T, R, TPL, P>;
+    T ev[2][Epi::G][Epi::NV];
+    // FP64, P > 1: the first group of epilogue inputs is requested before the transforms (its latency
+    // then hides behind them; the registers are free at the occupancy FP64 blocks run at)
+    constexpr bool EARLY = sizeof(T) == 8 && P > 1 && LB_EPI_EARLY_F64;
+    if constexpr (EARLY) {
+        if (active) epi.load(0, ev[0]);
+    }
     // X[q] <- -c v_x D_x f_i - (c/tau) f_i on the block's two rows; all P lines are loaded
     // before the first transform so their memory latencies overlap
     cpx<T> X[P][R];
@@ -558,25 +585,9 @@ pop_x_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
     // keep the epilogue's loads out of the transforms above (their registers would be live there)
     asm volatile("" ::: "memory");
 #endif
-    int pop[P];
-#pragma unroll
-    for (int q = 0; q < P; ++q) pop[q] = D.xorder[w.job * P + q];
-    const bool has_base = st.base_field >= 0;
-    const uint32_t cf[7] = {fofs<T>(I, RHO), fofs<T>(I, UX), fofs<T>(I, UY), fofs<T>(I, TT),
-                            fofs<T>(I, BX), fofs<T>(I, BY), fofs<T>(I, CT)};
-    uint32_t basep[P], outp[P];
-#pragma unroll
-    for (int q = 0; q < P; ++q) {
-        // without a base (the bare right-hand side) the partial block is read and discarded
-        basep[q] = fofs<T>(I, has_base ? st.base_field + pop[q] : F_P + pop[q]);
-        // out may equal the base block (second stage writes f^{n+1} over f^n per cell)
-        outp[q] = fofs<T>(I, (D.vy[pop[q]] == T(0) ? st.out_field : F_P) + pop[q]);
-    }
-    const bool row1 = 2 * line + 1 < ny;
-    const PopXEpi<T, R, TPL, P> epi{D, pop, arena<T>(I), cf, basep, outp, has_base, line, t, nx, row1,
-                                    T(I.b), c, inv_tau};
+    if constexpr (!EARLY) epi.load(0, ev[0]);
     // pairs of populations with v_x != 0 are x mirrors, the others y mirrors (uniform per block)
-    epi.run(X, P > 1 && D.vx[pop[0]] == T(0));
+    epi.run(X, P > 1 && D.vx[pop[0]] == T(0), ev);
 }
 
 // Population y pass: one block = (instance, tile of column pairs, population i with v_y != 0).
