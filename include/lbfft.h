@@ -130,6 +130,15 @@ lb_status lb_conservation_history(lb_ctx* ctx, int inst, int max_entries, double
 lb_status lb_get_f(lb_ctx* ctx, int inst, double* f);
 lb_status lb_set_f(lb_ctx* ctx, int inst, const double* f);
 
+/* Replace the state of instance inst by the equilibrium of the given macroscopic fields:
+ * f = f^eq(rho, u, T) of the seven kinetic moments (Sec. 2.1), as lb_init does for the initial
+ * condition.  rho, ux, uy, T: host float64 arrays [ny][nx], read only.  Used to restart a run
+ * at another temperature (the coexistence runs of Sec. 3.1 lower T once the phases have
+ * settled).  LB_E_ARG if a pointer is NULL or a cell has rho <= 0, T <= 0, 1 - vdw_b rho <= 0
+ * or a non-finite value (the state is then unchanged).  Synchronises. */
+lb_status lb_set_moments(lb_ctx* ctx, int inst, const double* rho, const double* ux,
+                         const double* uy, const double* T);
+
 /* Diagnostics on the current state of instance inst, each computed with the same kernels as
  * lb_step and copied to host arrays [ny][nx]; they synchronise and leave the state unchanged.
  *  lb_force_coefficients: B_x, B_y and C + C_q of Eq. (2) from the moments of the current f.

@@ -491,6 +491,21 @@ lb_status field_from_host(lb_ctx* c, int inst, int fid, const double* src, int64
     return LB_OK;
 }
 
+// Host (rho, u_x, u_y, T) fields of an instance: present, finite, rho > 0, T > 0, 1 - b_w rho > 0.
+lb_status check_moment_fields(const lb_params& q, int k, const double* rho, const double* ux,
+                              const double* uy, const double* T) {
+    if (!rho || !ux || !uy || !T) return fail(LB_E_ARG, "instance %d: null field", k);
+    const int64_t nc = (int64_t)q.nx * q.ny;
+    for (int64_t e = 0; e < nc; ++e) {
+        const double r = rho[e], t = T[e];
+        if (!(r > 0) || !(t > 0) || !(1.0 - q.vdw_b * r > 0) || !std::isfinite(ux[e]) ||
+            !std::isfinite(uy[e]) || !std::isfinite(r) || !std::isfinite(t))
+            return fail(LB_E_ARG, "instance %d cell %lld: need rho > 0, T > 0, 1 - vdw_b rho > 0 "
+                        "and finite u", k, (long long)e);
+    }
+    return LB_OK;
+}
+
 lb_status validate_params(const lb_params& q, int k) {
     if (!grid_ok(q.nx, q.ny))
         return fail(LB_E_SIZE, "instance %d: unsupported grid %dx%d (each side 2^a or 3*2^a in "
@@ -503,6 +518,26 @@ lb_status validate_params(const lb_params& q, int k) {
     if (q.vdw_b < 0) return fail(LB_E_ARG, "instance %d: vdw_b must be >= 0", k);
     if (q.hist_len < 0 || q.hist_len > (1 << 24))
         return fail(LB_E_ARG, "instance %d: hist_len must be in [0, 2^24]", k);
+    return LB_OK;
+}
+
+// Stage host (rho, u_x, u_y, T) as float64 in the F_B block of instance k, then set
+// f = f^eq(rho, u, T) in F_A (Sec. 2.1).  Fields already checked.  Synchronous.
+lb_status state_from_moments(lb_ctx* c, int k, const double* rho, const double* ux, const double* uy,
+                             const double* T) {
+    const InstDesc& I = c->hinst[k];
+    unsigned char* stage = reinterpret_cast<unsigned char*>(I.base) + (size_t)F_B * I.ncell * c->wbytes();
+    const double* src[4] = {rho, ux, uy, T};
+    for (int f = 0; f < 4; ++f)
+        LB_HIP(hipMemcpyAsync(stage + (size_t)f * I.ncell * 8, src[f], I.ncell * 8,
+                              hipMemcpyHostToDevice, c->stream));
+    LB_HIP(hipStreamSynchronize(c->stream));
+    const LaunchSet L = set_one(*c, k, c->stream);
+    if (c->prec == LB_FP64)
+        LB_HIP(launch_init<double>(L, c->dev<DvmConst<double>>(c->lay.dvm64)));
+    else
+        LB_HIP(launch_init<float>(L, c->dev<DvmConst<double>>(c->lay.dvm64)));
+    LB_HIP(hipStreamSynchronize(c->stream));
     return LB_OK;
 }
 
@@ -534,15 +569,8 @@ lb_status lb_init(lb_ctx** out, int n_inst, const lb_params* p, const lb_dvm* dv
     for (int k = 0; k < n_inst; ++k) {
         lb_status s = validate_params(p[k], k);
         if (s != LB_OK) return s;
-        if (!rho0[k] || !ux0[k] || !uy0[k] || !T0[k]) return fail(LB_E_ARG, "instance %d: null field", k);
-        const int64_t nc = (int64_t)p[k].nx * p[k].ny;
-        for (int64_t e = 0; e < nc; ++e) {
-            const double r = rho0[k][e], t = T0[k][e];
-            if (!(r > 0) || !(t > 0) || !(1.0 - p[k].vdw_b * r > 0) || !std::isfinite(ux0[k][e]) ||
-                !std::isfinite(uy0[k][e]) || !std::isfinite(r) || !std::isfinite(t))
-                return fail(LB_E_ARG, "instance %d cell %lld: need rho > 0, T > 0, 1 - vdw_b rho > 0 "
-                            "and finite u", k, (long long)e);
-        }
+        s = check_moment_fields(p[k], k, rho0[k], ux0[k], uy0[k], T0[k]);
+        if (s != LB_OK) return s;
     }
     Layout lay = make_layout(n_inst, p, prec);
     if (ws_bytes < lay.total)
@@ -703,31 +731,10 @@ lb_status lb_init(lb_ctx** out, int n_inst, const lb_params* p, const lb_dvm* dv
             st = fail(LB_E_HIP, "table kernel: %s", hipGetErrorString(e));
         }
     }
-    // initial condition: stage (rho, ux, uy, T) as float64 in the F_B block, then f = f^eq
+    // initial condition: f = f^eq(rho0, u0, T0)
     for (int k = 0; ok && k < n_inst; ++k) {
-        const InstDesc& I = c->hinst[k];
-        unsigned char* stage = reinterpret_cast<unsigned char*>(I.base) + (size_t)F_B * I.ncell * w;
-        const double* src[4] = {rho0[k], ux0[k], uy0[k], T0[k]};
-        for (int f = 0; ok && f < 4; ++f) {
-            hipError_t e = hipMemcpyAsync(stage + (size_t)f * I.ncell * 8, src[f], I.ncell * 8,
-                                          hipMemcpyHostToDevice, c->stream);
-            if (e != hipSuccess) {
-                ok = false;
-                st = fail(LB_E_HIP, "IC upload: %s", hipGetErrorString(e));
-            }
-        }
-        if (ok) {
-            hipError_t e = hipStreamSynchronize(c->stream);
-            if (e == hipSuccess) {
-                LaunchSet L = set_one(*c, k, c->stream);
-                e = prec == LB_FP64 ? launch_init<double>(L, c->dev<DvmConst<double>>(lay.dvm64))
-                                    : launch_init<float>(L, c->dev<DvmConst<double>>(lay.dvm64));
-            }
-            if (e != hipSuccess) {
-                ok = false;
-                st = fail(LB_E_HIP, "init kernel: %s", hipGetErrorString(e));
-            }
-        }
+        st = state_from_moments(c, k, rho0[k], ux0[k], uy0[k], T0[k]);
+        ok = st == LB_OK;
     }
     if (ok) {
         hipError_t e = hipStreamSynchronize(c->stream);
@@ -927,6 +934,14 @@ lb_status lb_set_f(lb_ctx* c, int inst, const double* f) {
     if (s != LB_OK) return s;
     if (!f) return fail(LB_E_ARG, "f is NULL");
     return field_from_host(c, inst, F_A, f, 16);
+}
+
+lb_status lb_set_moments(lb_ctx* c, int inst, const double* rho, const double* ux, const double* uy,
+                         const double* T) {
+    lb_status s = check_inst(c, inst);
+    if (s != LB_OK) return s;
+    if ((s = check_moment_fields(c->p[inst], inst, rho, ux, uy, T)) != LB_OK) return s;
+    return state_from_moments(c, inst, rho, ux, uy, T);
 }
 
 lb_status lb_force_coefficients(lb_ctx* c, int inst, double* Bx, double* By, double* C) {

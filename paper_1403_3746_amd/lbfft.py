@@ -19,7 +19,7 @@ _STATUS = {0: "LB_OK", -1: "LB_E_ARG", -2: "LB_E_SIZE", -3: "LB_E_NOMEM", -4: "L
            -5: "LB_E_NONFINITE", -6: "LB_E_STATE"}
 
 EXPORTS = ("lb_workspace_bytes", "lb_init", "lb_step", "lb_sync", "lb_moments", "lb_conservation", "lb_conservation_history",
-           "lb_get_f", "lb_set_f", "lb_force_coefficients", "lb_rhs", "lb_derivative",
+           "lb_get_f", "lb_set_f", "lb_set_moments", "lb_force_coefficients", "lb_rhs", "lb_derivative",
            "lb_step_timed", "lb_plan_info", "lb_free", "lb_last_error")
 PASS_NAMES = ("moments", "macro_x1", "macro_y1", "stress", "macro_x2", "macro_y2", "finalize",
               "pop_x", "pop_y")
@@ -70,6 +70,7 @@ def load():
                                             ctypes.POINTER(ctypes.c_longlong)]
     lib.lb_get_f.argtypes = [V, I, dp]
     lib.lb_set_f.argtypes = [V, I, dp]
+    lib.lb_set_moments.argtypes = [V, I, dp, dp, dp, dp]
     lib.lb_force_coefficients.argtypes = [V, I, dp, dp, dp]
     lib.lb_rhs.argtypes = [V, I, dp]
     lib.lb_derivative.argtypes = [V, I, I, I, dp, dp]
@@ -178,6 +179,11 @@ def lb_set_f(ctx, inst, f):
     _check(load().lb_set_f(ctx, inst, _dptr(f)))
 
 
+def lb_set_moments(ctx, inst, rho, ux, uy, T):
+    a = [np.ascontiguousarray(x, dtype=np.float64) for x in (rho, ux, uy, T)]
+    _check(load().lb_set_moments(ctx, inst, *(_dptr(x) for x in a)))
+
+
 def lb_force_coefficients(ctx, inst, shape):
     out = [np.empty(shape) for _ in range(3)]
     _check(load().lb_force_coefficients(ctx, inst, *[_dptr(a) for a in out]))
@@ -259,6 +265,11 @@ class Sim:
 
     def set_f(self, f, inst=0):
         lb_set_f(self.ctx, inst, f)
+
+    def set_moments(self, rho, ux, uy, T, inst=0):
+        shape = self.shapes[inst]
+        a = [np.broadcast_to(np.asarray(x, dtype=np.float64), shape) for x in (rho, ux, uy, T)]
+        lb_set_moments(self.ctx, inst, *a)
 
     def force_coefficients(self, inst=0):
         return lb_force_coefficients(self.ctx, inst, self.shapes[inst])

@@ -18,6 +18,10 @@ int main() {
     st = lb_step(c, 3); printf("step %d\n", st);
     double ms[LB_NPASS]; st = lb_step_timed(c, 2, ms); printf("timed %d\n", st);
     double out[4]; st = lb_conservation(c, 0, out); printf("cons %d\n", st);
+    std::vector<double> T2(n * n, 0.5);
+    st = lb_set_moments(c, 0, rho.data(), ux.data(), uy.data(), T2.data()); printf("setmom %d\n", st);
+    T2[7] = -1.0;
+    st = lb_set_moments(c, 0, rho.data(), ux.data(), uy.data(), T2.data()); printf("setmom_bad %d\n", st);
     lb_free(c); free(mem);
     // batch of two classes with history
     lb_params q[3] = {p, p, p}; q[1].nx = 96; q[1].ny = 96; q[2].hist_len = 8;

@@ -29,3 +29,4 @@ def test_host_runtime_under_sanitizers(tmp_path):
     assert r.returncode == 0, (r.stdout + r.stderr)[-4000:]
     lines = r.stdout.split("\n")
     assert "init 0 " in lines and "init2 0 " in lines and "done" in lines, r.stdout
+    assert "setmom 0" in lines and "setmom_bad -1" in lines, r.stdout
