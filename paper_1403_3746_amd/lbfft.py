@@ -158,13 +158,16 @@ def lb_conservation(ctx, inst):
     return out
 
 
-def lb_conservation_history(ctx, inst, max_entries):
-    """(first_step, array[n, 4]) of the per-step conservation integrals kept on the GPU."""
+def lb_conservation_history(ctx, inst, max_entries, allow_nonfinite=False):
+    """(first_step, array[n, 4]) of the per-step conservation integrals kept on the GPU.  With
+    allow_nonfinite the entries are returned even if some are NaN/Inf (a run that blew up)."""
     out = np.empty((max(max_entries, 1), 4))
     n = ctypes.c_int()
     first = ctypes.c_longlong()
-    _check(load().lb_conservation_history(ctx, inst, max_entries, _dptr(out), ctypes.byref(n),
-                                          ctypes.byref(first)))
+    st = load().lb_conservation_history(ctx, inst, max_entries, _dptr(out), ctypes.byref(n),
+                                        ctypes.byref(first))
+    if not (allow_nonfinite and st == LB_E_NONFINITE):
+        _check(st)
     return first.value, out[: n.value].copy()
 
 
@@ -257,8 +260,8 @@ class Sim:
     def conservation(self, inst=0):
         return lb_conservation(self.ctx, inst)
 
-    def history(self, inst=0, max_entries=1 << 20):
-        return lb_conservation_history(self.ctx, inst, max_entries)
+    def history(self, inst=0, max_entries=1 << 20, allow_nonfinite=False):
+        return lb_conservation_history(self.ctx, inst, max_entries, allow_nonfinite)
 
     def get_f(self, inst=0):
         return lb_get_f(self.ctx, inst, self.shapes[inst])
