@@ -879,9 +879,11 @@ lb_status lb_conservation(lb_ctx* c, int inst, double out[4]) {
     if (s != LB_OK) return s;
     if (!out) return fail(LB_E_ARG, "out is NULL");
     const LaunchSet L = set_one(*c, inst, c->stream);
-    LB_HIP(moments(*c, L, F_A));
-    LB_HIP(macro(*c, L, 0, c->j_x1, c->n_x1));
-    LB_HIP(macro(*c, L, 1, c->j_y1, c->n_y1));
+    // the same passes (fused or not) as the step, so the on-demand sums equal the recorded ones
+    const StageArgs st{F_A, -1, -1, 0.0, 0};
+    LB_HIP(run_pass(*c, L, LB_PASS_MOMENTS, st));
+    LB_HIP(run_pass(*c, L, LB_PASS_MACRO_X1, st));
+    LB_HIP(run_pass(*c, L, LB_PASS_MACRO_Y1, st));
     LB_HIP(c->prec == LB_FP64 ? launch_conserve<double>(L, 0) : launch_conserve<float>(L, 0));
     double r[5];
     LB_HIP(hipMemcpyAsync(r, c->hinst[inst].cons, sizeof(r), hipMemcpyDeviceToHost, c->stream));
