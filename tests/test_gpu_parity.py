@@ -269,3 +269,21 @@ def test_conservation_history_ring_wraps(torch_cuda):
         sim.history(1)
     assert e.value.status == lbfft.LB_E_STATE
     sim.close()
+
+
+@pytest.mark.parametrize("ppb", ["1", "2", "4"])
+def test_full_step_square_sizes_of_three_times_pow2(torch_cuda, monkeypatch, ppb):
+    # one RK2 step of square 3*2^a grids (radix-12 lines, fused x+y passes, every x-pass plan)
+    # against the oracle; the derivative test covers these lengths in the macroscopic passes only
+    monkeypatch.setenv("LBFFT_PPB", ppb)
+    for n in (24, 96, 192, 384):
+        p = W.base_params(q=-0.004, zeta=1e-3)
+        ic = W.smooth_random(n, n, 100 + n, T0=0.52)
+        sim = _sim([(p, ic)])
+        f = model.rk2_step(model.init_equilibrium(*ic, p), p)
+        sim.step(1)
+        g = sim.get_f()
+        err = np.abs(g - f).max() / np.abs(f).max()
+        say(f"full step {n}x{n} pops/block {ppb}: rel err {err:.2e}")
+        assert err < 1e-12, (n, ppb, err)
+        sim.close()
