@@ -3,9 +3,10 @@
 //
 // One Runge-Kutta stage R(f) (Eq. 1, Sec. 2.3) runs as:
 //   moments      pointwise   f -> rho, u, T                              (Sec. 2.1)
-//   macro X1|Y1  x, y lines  first and second derivatives of rho, T, u   (Eq. 3) (concurrent)
+//   macro X1|Y1  x, y lines  first and second derivatives of rho, T, u   (Eq. 3) (independent:
+//                            one fused launch on square grids)
 //   stress       pointwise   S, div u, q rho T grad T, most of C         (Eq. 2, Sec. 2.2)
-//   macro X2|Y2  x, y lines  derivatives of S, div u, Q                  (Eq. 3) (concurrent)
+//   macro X2|Y2  x, y lines  derivatives of S, div u, Q                  (Eq. 3) (likewise)
 //   finalize     pointwise   B = div S/(rho T), C + C_q                  (Eq. 2)
 //   pop X        x lines     per population: v_x d_x f, f^eq, I_i, BGK, RK axpy -> final (axis-x
 //                            populations) or partial (the rest)
@@ -18,9 +19,6 @@
 #include "lb_fft.h"
 #include "lb_types.h"
 
-#ifndef LB_EPI_GROUP
-#define LB_EPI_GROUP 4   // epilogue positions whose field loads may be hoisted together
-#endif
 #ifndef LB_YSEG
 #define LB_YSEG 128      // bytes of each row a y-pass tile covers (2 * lines per block * word)
 #endif
@@ -376,9 +374,6 @@ __device__ __forceinline__ T feq_pop(const DvmConst<T>& D, int i, T rho, T ux, T
 #ifndef LB_EPI_EARLY_F64
 #define LB_EPI_EARLY_F64 1
 #endif
-#ifndef LB_EPI_FENCE
-#define LB_EPI_FENCE 1
-#endif
 #ifndef LB_EPI_CELLS_F64
 #define LB_EPI_CELLS_F64 2
 #endif
@@ -581,10 +576,9 @@ pop_x_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
         }
     }
     if (!active) return;
-#if LB_EPI_FENCE
-    // keep the epilogue's loads out of the transforms above (their registers would be live there)
+    // keep the (other) epilogue loads out of the transforms above: their registers would be
+    // live there
     asm volatile("" ::: "memory");
-#endif
     if constexpr (!EARLY) epi.load(0, ev[0]);
     // pairs of populations with v_x != 0 are x mirrors, the others y mirrors (uniform per block)
     epi.run(X, P > 1 && D.vx[pop[0]] == T(0), ev);

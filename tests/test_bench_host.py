@@ -1,0 +1,47 @@
+"""bench.py's bookkeeping without a GPU: algorithmic words, the fused x+y passes, the roofline
+fields of the JSON line, and the one-GPU guard."""
+import json
+import os
+import subprocess
+import sys
+
+import bench
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def test_words_per_step():
+    # stage 1 and stage 2 together; pop_x averages its 39 (stage 1) and 55 (stage 2) words
+    assert bench.WORDS_PER_STEP == 2 * sum(bench.ALG_WORDS.values()) == 328
+    assert bench.ALG_WORDS["pop_x"] == (39 + 55) // 2
+
+
+def test_roofline_of_fused_and_separate_passes():
+    cells = 512 * 512
+    passes = {"moments": 0.0074, "macro_x1": 0.0142, "macro_y1": 0.0, "stress": 0.0057,
+              "macro_x2": 0.0104, "macro_y2": 0.0, "finalize": 0.0048, "pop_x": 0.0213,
+              "pop_y": 0.0148}
+    res = dict(cells=cells, passes=passes, mlups=1500.0)
+    r = bench.roofline(res, 8, "no_such_workload")
+    assert r["kernel"] == "pop_x" and r["bound"] == "hbm" and r["unit"] == "GB/s"
+    # fused launches are reported under their own names with both passes' words
+    assert "macro_xy1" in r["passes"] and "macro_x1" not in r["passes"]
+    xy1 = 18 * 8 * cells / (0.0142e-3) / 1e9
+    assert abs(r["passes"]["macro_xy1"]["gbs"] - round(xy1, 1)) < 0.2
+    alg = 47 * 8 * cells
+    assert r["alg_bytes_per_launch"] == alg
+    assert abs(r["achieved"] - alg / 0.0213e-3 / 1e9) < 0.2
+    assert abs(r["frac"] - r["achieved"] / 8000.0) < 1e-4
+    assert r["traffic"] is None          # no counters for an unknown workload
+    assert abs(r["step_frac"] - 1500e6 * 328 * 8 / 1e9 / 8000) < 1e-4
+    # separate launches (non-square grids) keep the x and y names
+    passes.update(macro_y1=0.0107, macro_y2=0.0079)
+    r = bench.roofline(dict(res, passes=passes), 8, "no_such_workload")
+    assert {"macro_x1", "macro_y1", "macro_x2", "macro_y2"} <= set(r["passes"])
+
+
+def test_more_than_one_gpu_is_refused():
+    out = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                         capture_output=True, text=True, timeout=120)
+    assert out.returncode == 2
+    assert "one GPU" in json.loads(out.stdout.strip().splitlines()[-1])["error"]
