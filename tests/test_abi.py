@@ -62,3 +62,23 @@ def test_init_rejects_bad_arguments_without_gpu():
     with pytest.raises(lbfft.LBError) as e:
         lbfft.lb_init(prm, lbfft.make_dvm(), lbfft.LB_FP64, [rho], [ux], [uy], [T], 256, 1024, 0)
     assert e.value.status == lbfft.LB_E_SIZE
+
+
+def test_edge_cases_rejected_on_the_host():
+    p = W.base_params()
+    rho, ux, uy, T = W.slab(64, 64, 0.5)
+    prm = [lbfft.make_params(p, 64, 64)]
+    # an empty batch needs no workspace and cannot be initialised
+    assert lbfft.lb_workspace_bytes([], lbfft.LB_FP64) == 0
+    with pytest.raises(lbfft.LBError) as e:
+        lbfft.lb_init([], lbfft.make_dvm(), lbfft.LB_FP64, [], [], [], [], 256, 1 << 30, 0)
+    assert e.value.status == lbfft.LB_E_ARG
+    # without eta on ring 1 the moment matrix of the seven kinetic moments is singular
+    with pytest.raises(lbfft.LBError) as e:
+        lbfft.lb_init(prm, lbfft.make_dvm(dict(eta0=0.0)), lbfft.LB_FP64, [rho], [ux], [uy], [T],
+                      256, 1 << 30, 0)
+    assert e.value.status == lbfft.LB_E_ARG and "singular" in str(e.value)
+    # calls on a null context fail cleanly
+    with pytest.raises(lbfft.LBError) as e:
+        lbfft.lb_set_moments(None, 0, rho, ux, uy, T)
+    assert e.value.status == lbfft.LB_E_ARG
