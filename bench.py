@@ -9,7 +9,8 @@ HBM before timing starts; the timed region replays the captured step graph.
 
 roofline: algorithmic HBM words per cell of each pass (listed in ALG_WORDS) times cells, over the
 pass's mean launch duration from HIP events recorded on the library's stream during a second run
-of steps (lb_step_timed); the dominant pass (largest time per step) is reported.
+of steps (lb_step_timed); the dominant pass (largest time per step) is reported, and beside it the
+HBM bytes per launch the rocprofv3 counters measured (profiles/traffic.json) over the same time.
 cpu_baseline: the FP64 CPU oracle stepping the same 512x512 initial condition for a bounded number
 of steps on the host cores.
 """
@@ -111,8 +112,13 @@ def roofline(res, word_bytes, workload):
     dom = max(per_pass, key=lambda k: per_pass[k]["ms"])
     d = per_pass[dom]
     traffic = load_traffic(workload, dom)
+    # the same launch priced by the HBM bytes the rocprofv3 counters measured (when they were
+    # taken on the current kernel sources)
+    measured = None if traffic is None else traffic / (d["ms"] * 1e-3) / 1e9
     return dict(bound="hbm", kernel=dom, achieved=round(d["gbs"], 1), peak=HBM_PEAK_GBS,
                 unit="GB/s", frac=round(d["gbs"] / HBM_PEAK_GBS, 4), traffic=traffic,
+                measured_gbs=None if measured is None else round(measured, 1),
+                measured_frac=None if measured is None else round(measured / HBM_PEAK_GBS, 4),
                 alg_bytes_per_launch=d["alg_bytes"], mean_launch_ms=round(d["ms"], 5),
                 passes={k: dict(ms=round(v["ms"], 5), gbs=round(v["gbs"], 1)) for k, v in per_pass.items()},
                 step_frac=round(res["mlups"] * 1e6 * WORDS_PER_STEP * word_bytes / 1e9 / HBM_PEAK_GBS, 4))
@@ -135,7 +141,16 @@ def cpu_baseline(instances, budget_s=15.0):
     dt = time.perf_counter() - t0
     cells = ic[0].size
     spectral.set_workers(1)
+    model_name = None
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                model_name = line.split(":", 1)[1].strip()
+                break
+    except OSError:
+        pass
     return dict(value=round(cells * n / dt / 1e6, 4), unit="MLUPS", cores=workers, kind="oracle",
+                cpu=model_name,
                 sample=f"FP64 oracle, {ic[0].shape[1]}x{ic[0].shape[0]} quench, {n} RK2 steps after 1 "
                        f"warm-up step, scipy.fft workers={workers}")
 

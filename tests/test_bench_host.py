@@ -32,7 +32,7 @@ def test_roofline_of_fused_and_separate_passes():
     assert r["alg_bytes_per_launch"] == alg
     assert abs(r["achieved"] - alg / 0.0213e-3 / 1e9) < 0.2
     assert abs(r["frac"] - r["achieved"] / 8000.0) < 1e-4
-    assert r["traffic"] is None          # no counters for an unknown workload
+    assert r["traffic"] is None and r["measured_frac"] is None   # no counters for this workload
     assert abs(r["step_frac"] - 1500e6 * 328 * 8 / 1e9 / 8000) < 1e-4
     # separate launches (non-square grids) keep the x and y names
     passes.update(macro_y1=0.0107, macro_y2=0.0079)
@@ -45,3 +45,12 @@ def test_more_than_one_gpu_is_refused():
                          capture_output=True, text=True, timeout=120)
     assert out.returncode == 2
     assert "one GPU" in json.loads(out.stdout.strip().splitlines()[-1])["error"]
+
+
+def test_measured_traffic_fraction(monkeypatch):
+    monkeypatch.setattr(bench, "load_traffic", lambda w, p: 119_000_000)
+    res = dict(cells=512 * 512, passes={"pop_x": 0.0211, "pop_y": 0.0147}, mlups=1500.0)
+    r = bench.roofline(res, 8, "quench512_fp64")
+    assert r["traffic"] == 119_000_000
+    assert abs(r["measured_gbs"] - 119e6 / 0.0211e-3 / 1e9) < 0.1
+    assert abs(r["measured_frac"] - r["measured_gbs"] / 8000.0) < 1e-4
