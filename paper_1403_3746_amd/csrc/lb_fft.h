@@ -187,6 +187,21 @@ __device__ __forceinline__ cpx<T> ldc(twptr<T> p, int idx) {
     return cpx<T>{p[idx].re, p[idx].im};
 }
 
+// Barrier between the LDS exchanges of a transform.  WAVE: every line the block holds belongs to
+// one wave (x blocks of lines of at most 64 threads), so only the wave's own LDS accesses need
+// ordering: a wave's LDS instructions execute in issue order, and the fences keep the compiler
+// from moving accesses across; the block's waves then run their transforms independently.
+template <bool WAVE>
+__device__ __forceinline__ void line_sync() {
+    if constexpr (WAVE) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    } else {
+        __syncthreads();
+    }
+}
+
 // Number of twiddles a radix-r butterfly reads: radix 8 reads w, w^2, w^4 and forms the rest by at
 // most two products; radix 4 reads w, w^2; radix 2 and 3 read w^q, q = 1..r-1, directly.
 constexpr int tw_reads(int r) { return r == 8 ? 3 : (r == 4 ? 2 : r - 1); }
@@ -286,7 +301,7 @@ struct TwSet {
 // Pass S of the plan: one Stockham pass of radix r = P.r[S] with Ns = product of the previous radices.
 // LDS element i of the line lives at lds[lds_idx(i) * LS]: LS = 1 for line-contiguous storage,
 // LS = lines per block for lines interleaved word by word (lanes of neighbouring lines adjacent).
-template <typename T, int N, int R, int S, bool INV, bool FROM_REG, bool TO_REG, int LS>
+template <typename T, int N, int R, int S, bool INV, bool FROM_REG, bool TO_REG, int LS, bool WAVE = false>
 __device__ __forceinline__ void stockham_pass(cpx<T> (&v)[R], cpx<T>* lds, int t, const TwSet<T, N, R>& tw) {
     constexpr int r = TwSet<T, N, R>::P.r[S];
     constexpr int Ns = plan_ns(TwSet<T, N, R>::P, S);
@@ -305,7 +320,7 @@ __device__ __forceinline__ void stockham_pass(cpx<T> (&v)[R], cpx<T>* lds, int t
 #pragma unroll
             for (int q = 0; q < r; ++q) a[b * r + q] = lds[lds_idx(j + q * (N / r)) * LS];
         }
-        __syncthreads();
+        line_sync<WAVE>();
     }
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
@@ -332,14 +347,15 @@ __device__ __forceinline__ void stockham_pass(cpx<T> (&v)[R], cpx<T>* lds, int t
             for (int q = 0; q < r; ++q) lds[lds_idx(base + q * Ns) * LS] = a[b * r + q];
         }
     }
-    if constexpr (!TO_REG) __syncthreads();
+    if constexpr (!TO_REG) line_sync<WAVE>();
 }
 
 // Pass S for Q lines at once (line q's LDS region starts `stride` complex words after line
 // q-1's): one LDS round trip and one pair of barriers for all Q lines, the butterflies' twiddle
 // powers formed once and applied to every line, and Q independent butterflies per twiddle set for
 // the scheduler to interleave.
-template <typename T, int N, int R, int S, bool INV, bool FROM_REG, bool TO_REG, int LS, int Q>
+template <typename T, int N, int R, int S, bool INV, bool FROM_REG, bool TO_REG, int LS, int Q,
+          bool WAVE = false>
 __device__ __forceinline__ void stockham_pass_n(cpx<T> (&v)[Q][R], cpx<T>* lds, int stride, int t,
                                                 const TwSet<T, N, R>& tw) {
     constexpr int r = TwSet<T, N, R>::P.r[S];
@@ -363,7 +379,7 @@ __device__ __forceinline__ void stockham_pass_n(cpx<T> (&v)[Q][R], cpx<T>* lds, 
 #pragma unroll
                 for (int q = 0; q < r; ++q) a[l][b * r + q] = lds[l * stride + lds_idx(j + q * (N / r)) * LS];
             }
-        __syncthreads();
+        line_sync<WAVE>();
     }
 #pragma unroll
     for (int b = 0; b < NB; ++b) {
@@ -398,10 +414,10 @@ __device__ __forceinline__ void stockham_pass_n(cpx<T> (&v)[Q][R], cpx<T>* lds, 
                 for (int q = 0; q < r; ++q) lds[l * stride + lds_idx(base + q * Ns) * LS] = a[l][b * r + q];
         }
     }
-    if constexpr (!TO_REG) __syncthreads();
+    if constexpr (!TO_REG) line_sync<WAVE>();
 }
 
-template <typename T, int N, int R, bool INV, int LS = 1>
+template <typename T, int N, int R, bool INV, int LS = 1, bool WAVE = false>
 struct LineFFT {
     static constexpr Plan P = make_plan(N, R);
     static constexpr int TPL = N / R;
@@ -415,14 +431,14 @@ struct LineFFT {
             constexpr bool last = (s == P.np - 1);
             constexpr bool from_reg = first && (r == R);
             constexpr bool to_reg = last && (r == R);
-            stockham_pass<T, N, R, s, INV, from_reg, to_reg, LS>(v, lds, t, tw);
+            stockham_pass<T, N, R, s, INV, from_reg, to_reg, LS, WAVE>(v, lds, t, tw);
             passes<s + 1>(v, lds, t, tw);
         }
     }
 
     // Transform the line in place: v[m] = x[t + m*TPL] on entry, X[t + m*TPL] on exit, with the
-    // thread's twiddles already loaded.  All threads of the workgroup must call this together (it
-    // contains barriers).
+    // thread's twiddles already loaded.  All threads of the workgroup (of the wave, with WAVE) must
+    // call this together (it contains barriers).
     __device__ __forceinline__ static void run(cpx<T> (&v)[R], cpx<T>* lds, int t, const Tw& tw) {
         if constexpr (P.np == 0) {
             return;
@@ -432,7 +448,7 @@ struct LineFFT {
             if constexpr (!first_reg) {
 #pragma unroll
                 for (int m = 0; m < R; ++m) lds[lds_idx(t + m * TPL) * LS] = v[m];
-                __syncthreads();
+                line_sync<WAVE>();
             }
             passes<0>(v, lds, t, tw);
             if constexpr (!last_reg) {
@@ -440,7 +456,7 @@ struct LineFFT {
                 for (int m = 0; m < R; ++m) v[m] = lds[lds_idx(t + m * TPL) * LS];
             }
             // the next transform may write LDS that slower threads are still reading
-            if constexpr (!(P.np == 1 && first_reg && last_reg)) __syncthreads();
+            if constexpr (!(P.np == 1 && first_reg && last_reg)) line_sync<WAVE>();
         }
     }
 
@@ -451,7 +467,7 @@ struct LineFFT {
             constexpr int r = P.r[s];
             constexpr bool from_reg = (s == 0) && (r == R);
             constexpr bool to_reg = (s == P.np - 1) && (r == R);
-            stockham_pass_n<T, N, R, s, INV, from_reg, to_reg, LS, Q>(v, lds, stride, t, tw);
+            stockham_pass_n<T, N, R, s, INV, from_reg, to_reg, LS, Q, WAVE>(v, lds, stride, t, tw);
             passes_n<s + 1, Q>(v, lds, stride, t, tw);
         }
     }
@@ -470,7 +486,7 @@ struct LineFFT {
                 for (int l = 0; l < Q; ++l)
 #pragma unroll
                     for (int m = 0; m < R; ++m) lds[l * stride + lds_idx(t + m * TPL) * LS] = v[l][m];
-                __syncthreads();
+                line_sync<WAVE>();
             }
             passes_n<0, Q>(v, lds, stride, t, tw);
             if constexpr (!last_reg) {
@@ -479,7 +495,7 @@ struct LineFFT {
 #pragma unroll
                     for (int m = 0; m < R; ++m) v[l][m] = lds[l * stride + lds_idx(t + m * TPL) * LS];
             }
-            if constexpr (!(P.np == 1 && first_reg && last_reg)) __syncthreads();
+            if constexpr (!(P.np == 1 && first_reg && last_reg)) line_sync<WAVE>();
         }
     }
 

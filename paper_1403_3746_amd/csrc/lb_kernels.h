@@ -16,12 +16,17 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "lb_decode.h"
 #include "lb_fft.h"
 #include "lb_types.h"
 
 #ifndef LB_YSEG
 #define LB_YSEG 128      // bytes of each row a y-pass tile covers (2 * lines per block * word)
 #endif
+#ifndef LB_YMAX_THREADS
+#define LB_YMAX_THREADS 512  // threads per y-pass block at most
+#endif
+#define LB_LDS_BYTES 163840      // LDS of one CU
 #ifndef LB_POPX_WAVES
 #define LB_POPX_WAVES 4  // waves per SIMD the single-population FP32 x pass must fit (register budget)
 #endif
@@ -36,8 +41,9 @@ namespace lbfft {
 
 // ---------------------------------------------------------------------------------------
 // Launch geometry of the line passes.  Small tiles keep many blocks in flight for a single grid;
-// y tiles span LPW column pairs (2*LPW*sizeof(T) bytes of each row), and neighbouring tiles run
-// on the same XCD (see decode_block) so partially used cache lines are reused from L2.
+// y tiles span LPW column pairs (2*LPW*sizeof(T) bytes of each row), and neighbouring tiles of one
+// field run together on the same XCD (decode_block_jm) so partially used cache lines are reused
+// from L2.
 // LDS: x blocks (lanes of one line adjacent) store each line contiguously; y blocks (lanes of
 // neighbouring lines adjacent) interleave their lines word by word (LS = LPW).
 template <typename T, int N, int DIR, int LPW_OVERRIDE = 0>
@@ -48,10 +54,12 @@ struct LineCfg {
     static constexpr int at_least(int l, int lo) { return l < lo ? lo : l; }
     // x: one line per block unless lines are short (then fill one wave)
     static constexpr int lpw_x() { return at_least(64 / TPL, 1); }
-    // y: LB_YSEG-byte row segments, at least one wave per block, at most 512 threads
+    // y: LB_YSEG-byte row segments, at least one wave per block, at most LB_YMAX_THREADS threads
+    // and the LDS of one CU (long lines get fewer column pairs)
     static constexpr int lpw_y() {
         int l = at_least(at_least(LB_YSEG / CB, 64 / TPL), 1);
-        return (l * TPL > 512) ? at_least(512 / TPL, 1) : l;
+        while (l > 1 && (l * TPL > LB_YMAX_THREADS || l * lds_line(N) * CB > LB_LDS_BYTES)) l /= 2;
+        return l;
     }
     static constexpr int LPW = LPW_OVERRIDE > 0 ? LPW_OVERRIDE : (DIR == 0 ? lpw_x() : lpw_y());
     static constexpr int WG = LPW * TPL;
@@ -61,48 +69,34 @@ struct LineCfg {
     __device__ __forceinline__ static int lds_base(int l) { return DIR == 0 ? l * lds_line(N) : l; }
 };
 
-// Decode the flat block index into (instance, tile, job).  Workgroups are dealt to the 8 XCDs
-// round-robin (block b runs on XCD b mod 8); each XCD gets a contiguous range of (instance, tile)
-// groups and runs all jobs of a group back to back, so the coefficient fields a group's jobs share
-// and the cache lines that neighbouring tiles split stay in that XCD's L2.
-struct BlockWork {
-    int inst_local, tile, job;
-    bool valid;
-};
-
-__host__ __device__ constexpr int groups_per_xcd(int ngroups) { return (ngroups + 7) / 8; }
-
-__device__ __forceinline__ BlockWork decode_block_at(int b, int ngroups, int ntiles, int njobs) {
-    const int xcd = b & 7;
-    const int slot = b >> 3;
-    const int gpx = groups_per_xcd(ngroups);
-    const int g_local = slot / njobs;
-    const int group = xcd * gpx + g_local;
-    BlockWork w;
-    w.job = slot % njobs;
-    w.valid = g_local < gpx && group < ngroups;
-    w.inst_local = group / ntiles;
-    w.tile = group % ntiles;
-    return w;
-}
-
 __device__ __forceinline__ BlockWork decode_block(int ngroups, int ntiles, int njobs) {
     return decode_block_at(blockIdx.x, ngroups, ntiles, njobs);
 }
 
-// Spectral multiplier kind mk applied to coefficient x of wavenumber k, including the 1/N of the
-// inverse transform:  M_D -> i (k/N) x,  M_DD -> -(k^2/N) x,  M_NONE -> 0.
-template <typename T>
-__device__ __forceinline__ cpx<T> spectral_mult(int mk, T k, T invN, cpx<T> x) {
-    if (mk == M_D) {
+#ifndef LB_WAVE_SYNC_X
+#define LB_WAVE_SYNC_X 1  // x macroscopic blocks of one-wave lines: per-wave LDS ordering
+#endif
+#ifndef LB_JOBMAJOR_X
+#define LB_JOBMAJOR_X 1   // x macroscopic passes: job-major block order
+#endif
+#ifndef LB_JOBMAJOR_Y
+#define LB_JOBMAJOR_Y 1   // y macroscopic and population passes: job-major block order
+#endif
+
+// Spectral multiplier kind MK applied to coefficient x of wavenumber k, including the 1/N of the
+// inverse transform:  M_D -> i (k/N) x,  M_DD -> -(k^2/N) x,  M_NONE -> 0.  The kind is a template
+// argument so that a line's R coefficients are scaled without a branch per element.
+template <int MK, typename T>
+__device__ __forceinline__ cpx<T> spectral_mult(T k, T invN, cpx<T> x) {
+    if constexpr (MK == M_D) {
         const T a = k * invN;
         return {-a * x.im, a * x.re};
-    }
-    if (mk == M_DD) {
+    } else if constexpr (MK == M_DD) {
         const T a = -k * k * invN;
         return {a * x.re, a * x.im};
+    } else {
+        return {T(0), T(0)};
     }
-    return {T(0), T(0)};
 }
 
 template <typename T>
@@ -214,10 +208,13 @@ __device__ __forceinline__ void macro_body(int b, const InstDesc* __restrict__ i
                                            const JobDesc* __restrict__ jobs, int njobs,
                                            cpx<T>* lds_all) {
     using C = LineCfg<T, N, DIR, LPW_>;
-    using FFT = LineFFT<T, N, C::R, false, C::LS>;
-    using IFFT = LineFFT<T, N, C::R, true, C::LS>;
+    // x blocks whose lines fit in a wave synchronise per wave (line_sync)
+    constexpr bool WAVE = DIR == 0 && C::TPL <= 64 && LB_WAVE_SYNC_X;
+    using FFT = LineFFT<T, N, C::R, false, C::LS, WAVE>;
+    using IFFT = LineFFT<T, N, C::R, true, C::LS, WAVE>;
     constexpr int R = C::R, TPL = C::TPL, LPW = C::LPW;
-    const BlockWork w = decode_block_at(b, ngroups, ntiles, njobs);
+    constexpr bool JM = DIR == 0 ? LB_JOBMAJOR_X : LB_JOBMAJOR_Y;
+    const BlockWork w = JM ? decode_block_jm(b, ngroups, ntiles, njobs) : decode_block_at(b, ngroups, ntiles, njobs);
     if (!w.valid) return;
     const InstDesc& I = insts[ilist[w.inst_local]];
     const JobDesc J = jobs[w.job];
@@ -249,8 +246,17 @@ __device__ __forceinline__ void macro_body(int b, const InstDesc* __restrict__ i
         const int outf = o == 0 ? J.out[0] : J.out[1];
         if (outf < 0) continue;
         const int mk = o == 0 ? J.mult[0] : J.mult[1];
+        // one uniform branch per output, outside the element loop
+        if (mk == M_D) {
 #pragma unroll
-        for (int m = 0; m < R; ++m) Y[m] = spectral_mult<T>(mk, kv[m], invN, X[m]);
+            for (int m = 0; m < R; ++m) Y[m] = spectral_mult<M_D>(kv[m], invN, X[m]);
+        } else if (mk == M_DD) {
+#pragma unroll
+            for (int m = 0; m < R; ++m) Y[m] = spectral_mult<M_DD>(kv[m], invN, X[m]);
+        } else {
+#pragma unroll
+            for (int m = 0; m < R; ++m) Y[m] = spectral_mult<M_NONE>(kv[m], invN, X[m]);
+        }
         IFFT::run(Y, lds, t, tws);
         if (!active) continue;
         LB_GLOBAL T* out = fieldp<T>(I, outf);
@@ -594,7 +600,8 @@ pop_y_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
     using C = LineCfg<T, N, 1>;
     constexpr int R = C::R, TPL = C::TPL, LPW = C::LPW;
     __shared__ cpx<T> lds_all[C::LDS];
-    const BlockWork w = decode_block(ngroups, ntiles, npops);
+    const BlockWork w = LB_JOBMAJOR_Y ? decode_block_jm(blockIdx.x, ngroups, ntiles, npops)
+                                      : decode_block(ngroups, ntiles, npops);
     if (!w.valid) return;
     const InstDesc& I = insts[ilist[w.inst_local]];
     const int i = pops[w.job];

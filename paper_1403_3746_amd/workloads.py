@@ -15,7 +15,7 @@ RHO_C = 3.5
 VDW_A = 9.0 / 49.0
 VDW_BW = 2.0 / 21.0
 
-# Allowed line lengths of the library: 2^a 3^b between 4 and 2048.
+# Line lengths of the ragged batch (the library takes 2^a or 3*2^a from 8 to 2048).
 RAGGED_SIZES = (64, 96, 128, 192, 256, 384, 512, 1024)
 
 

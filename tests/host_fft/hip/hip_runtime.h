@@ -8,3 +8,6 @@
 #define __forceinline__ inline
 extern thread_local std::barrier<>* host_workgroup_barrier;
 inline void __syncthreads() { host_workgroup_barrier->arrive_and_wait(); }
+// the per-wave ordering of the FFT's LDS exchanges: the workgroup barrier is a conservative stand-in
+#define __builtin_amdgcn_fence(order, scope) ((void)0)
+#define __builtin_amdgcn_wave_barrier() __syncthreads()

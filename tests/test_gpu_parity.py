@@ -287,3 +287,22 @@ def test_full_step_square_sizes_of_three_times_pow2(torch_cuda, monkeypatch, ppb
         say(f"full step {n}x{n} pops/block {ppb}: rel err {err:.2e}")
         assert err < 1e-12, (n, ppb, err)
         sim.close()
+
+
+@pytest.mark.parametrize("prec", ["fp64", "fp32"])
+def test_step_long_columns(torch_cuda, prec):
+    # tall grids: y lines of 768..2048 points (narrow column-pair tiles, blocks in job-major
+    # order), with the last tile partly empty where nx/2 is not a multiple of the tile width
+    tol = 1e-12 if prec == "fp64" else 2e-6
+    for ny, nx in ((768, 24), (1024, 24), (1536, 12), (2048, 12)):
+        p = W.base_params(q=-0.004, zeta=1e-3)
+        ic = W.smooth_random(nx, ny, 7 + ny, T0=0.52)
+        sim = _sim([(p, ic)], prec)
+        f_ref = model.init_equilibrium(*ic, p)
+        for _ in range(3):
+            f_ref = model.rk2_step(f_ref, p)
+        sim.step(3)
+        errs = field_errors(sim.get_f(), f_ref, _moments(p))
+        say(f"long columns {nx}x{ny} {prec} step 3: {errs}")
+        assert max(errs.values()) < tol, (ny, nx, errs)
+        sim.close()
