@@ -3,20 +3,29 @@
 // every line of a block forward (checked against a naive DFT) and back (checked against the
 // input), with the block shapes the kernels use: x blocks (lines contiguous in LDS, LS = 1) and
 // y blocks (lines interleaved word by word, LS = lines per block), one line at a time (run) and
-// Q lines together (run_n).  Prints one line per case: precision N layout Q fwd_err rt_err.
+// Q lines together (run_n), and x blocks of one-wave lines with per-wave ordering (WAVE).  Prints one line per case: precision N layout Q fwd_err rt_err.
 #include <cmath>
 #include <complex>
 #include <cstdio>
+#include <memory>
 #include <thread>
 #include <vector>
 
 #include "lb_fft.h"
 
 thread_local std::barrier<>* host_workgroup_barrier;
+thread_local std::barrier<>* host_wave_barrier;
+
+// One barrier per 64-lane wave of a workgroup of wg threads.
+static std::vector<std::unique_ptr<std::barrier<>>> wave_barriers(int wg) {
+    std::vector<std::unique_ptr<std::barrier<>>> w;
+    for (int b = 0; b < wg; b += 64) w.emplace_back(new std::barrier<>(std::min(64, wg - b)));
+    return w;
+}
 
 using namespace lbfft;
 
-template <typename T, int N, int LS, int LINES, int Q>
+template <typename T, int N, int LS, int LINES, int Q, bool WAVE = false>
 void run_case(const char* layout) {
     constexpr int R = default_R(N), TPL = N / R, WG = LINES * TPL;
     // LDS: x blocks give line l the region l*lds_line(N) (element i at lds_idx(i)); y blocks
@@ -27,22 +36,24 @@ void run_case(const char* layout) {
     for (size_t k = 0; k < x.size(); ++k)
         x[k] = {T(std::sin(0.37 * double(k * k % 1013) + 1.0)), T(std::cos(0.71 * double(k % 997)))};
     std::barrier<> bar(WG);
+    auto wbar = wave_barriers(WG);
     std::vector<std::thread> th;
     for (int tid = 0; tid < WG; ++tid)
         th.emplace_back([&, tid] {
             host_workgroup_barrier = &bar;
+            host_wave_barrier = wbar[tid / 64].get();
             const int l = LS == 1 ? tid / TPL : tid % LINES;
             const int t = LS == 1 ? tid % TPL : tid / LINES;
             cpx<T>* ld = lds.data() + (LS == 1 ? l * lds_line(N) : l);
-            typename LineFFT<T, N, R, false, LS>::Tw tw;
+            typename LineFFT<T, N, R, false, LS, WAVE>::Tw tw;
             tw.load(tab.data(), t);
             cpx<T> v[Q][R];
             for (int q = 0; q < Q; ++q)
                 for (int m = 0; m < R; ++m) v[q][m] = x[(q * LINES + l) * N + t + m * TPL];
             if constexpr (Q == 1) {
-                LineFFT<T, N, R, false, LS>::run(v[0], ld, t, tw);
+                LineFFT<T, N, R, false, LS, WAVE>::run(v[0], ld, t, tw);
             } else {
-                LineFFT<T, N, R, false, LS>::template run_n<Q>(v, ld, STRIDE, t, tw);
+                LineFFT<T, N, R, false, LS, WAVE>::template run_n<Q>(v, ld, STRIDE, t, tw);
             }
             for (int q = 0; q < Q; ++q)
                 for (int m = 0; m < R; ++m) {
@@ -51,9 +62,9 @@ void run_case(const char* layout) {
                     v[q][m].im *= T(1.0 / N);
                 }
             if constexpr (Q == 1) {
-                LineFFT<T, N, R, true, LS>::run(v[0], ld, t, tw);
+                LineFFT<T, N, R, true, LS, WAVE>::run(v[0], ld, t, tw);
             } else {
-                LineFFT<T, N, R, true, LS>::template run_n<Q>(v, ld, STRIDE, t, tw);
+                LineFFT<T, N, R, true, LS, WAVE>::template run_n<Q>(v, ld, STRIDE, t, tw);
             }
             for (int q = 0; q < Q; ++q)
                 for (int m = 0; m < R; ++m) z[(q * LINES + l) * N + t + m * TPL] = v[q][m];
@@ -109,6 +120,12 @@ void all_sizes() {
     run_case<T, 128, 8, 8, 1>("y");
     run_case<T, 384, 2, 2, 1>("y");
     run_case<T, 2048, 2, 2, 1>("y");
+    // x blocks of several one-wave lines ordered per wave (line_sync<true>): only the threads of
+    // one emulated wave synchronise, so a pass touching another wave's line would race
+    run_case<T, 96, 1, 8, 1, true>("xw");
+    run_case<T, 256, 1, 4, 1, true>("xw");
+    run_case<T, 512, 1, 8, 1, true>("xw");
+    run_case<T, 768, 1, 2, 1, true>("xw");
 }
 
 int main() {
