@@ -55,15 +55,18 @@ def kernel_source_hash():
     return h.hexdigest()[:16]
 
 
-def load_traffic(workload, pass_name):
+def load_traffic(workload, pass_name, pops_per_block=None):
     """HBM traffic per launch from committed rocprofv3 counter runs, if they were taken on the
-    current kernel sources (else None)."""
+    current kernel sources (else None).  The population x pass is looked up for the plan the run
+    used (populations per block), which the counter runs force one at a time."""
     path = os.path.join(ROOT, "profiles", "traffic.json")
     if not os.path.exists(path):
         return None
     try:
         d = json.load(open(path))
         ent = d.get(workload, {}).get(pass_name)
+        if ent and "plans" in ent:
+            ent = ent["plans"].get(str(pops_per_block))
         if ent and ent.get("kernel_source_hash") == kernel_source_hash():
             return ent["bytes_per_launch"]
     except Exception:
@@ -111,7 +114,7 @@ def roofline(res, word_bytes, workload):
         per_pass[name] = dict(ms=ms, alg_bytes=alg, gbs=alg / (ms * 1e-3) / 1e9)
     dom = max(per_pass, key=lambda k: per_pass[k]["ms"])
     d = per_pass[dom]
-    traffic = load_traffic(workload, dom)
+    traffic = load_traffic(workload, dom, res["plan"]["pops_per_block_x"])
     # the same launch priced by the HBM bytes the rocprofv3 counters measured (when they were
     # taken on the current kernel sources)
     measured = None if traffic is None else traffic / (d["ms"] * 1e-3) / 1e9

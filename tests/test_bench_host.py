@@ -21,7 +21,7 @@ def test_roofline_of_fused_and_separate_passes():
     passes = {"moments": 0.0074, "macro_x1": 0.0142, "macro_y1": 0.0, "stress": 0.0057,
               "macro_x2": 0.0104, "macro_y2": 0.0, "finalize": 0.0048, "pop_x": 0.0213,
               "pop_y": 0.0148}
-    res = dict(cells=cells, passes=passes, mlups=1500.0)
+    res = dict(cells=cells, passes=passes, mlups=1500.0, plan=dict(pops_per_block_x=2))
     r = bench.roofline(res, 8, "no_such_workload")
     assert r["kernel"] == "pop_x" and r["bound"] == "hbm" and r["unit"] == "GB/s"
     # fused launches are reported under their own names with both passes' words
@@ -48,9 +48,28 @@ def test_more_than_one_gpu_is_refused():
 
 
 def test_measured_traffic_fraction(monkeypatch):
-    monkeypatch.setattr(bench, "load_traffic", lambda w, p: 119_000_000)
-    res = dict(cells=512 * 512, passes={"pop_x": 0.0211, "pop_y": 0.0147}, mlups=1500.0)
+    monkeypatch.setattr(bench, "load_traffic", lambda w, p, ppb: 119_000_000 if ppb == 2 else None)
+    res = dict(cells=512 * 512, passes={"pop_x": 0.0211, "pop_y": 0.0147}, mlups=1500.0,
+               plan=dict(pops_per_block_x=2))
     r = bench.roofline(res, 8, "quench512_fp64")
     assert r["traffic"] == 119_000_000
     assert abs(r["measured_gbs"] - 119e6 / 0.0211e-3 / 1e9) < 0.1
     assert abs(r["measured_frac"] - r["measured_gbs"] / 8000.0) < 1e-4
+
+
+def test_traffic_is_looked_up_for_the_plan_and_sources(tmp_path, monkeypatch):
+    # the population x pass's counters are kept per plan; another plan or other kernel sources
+    # give no traffic figure
+    h = bench.kernel_source_hash()
+    d = {"w": {"moments": {"bytes_per_launch": 5, "kernel_source_hash": h},
+               "pop_x": {"plans": {"2": {"bytes_per_launch": 7, "kernel_source_hash": h},
+                                   "4": {"bytes_per_launch": 9, "kernel_source_hash": "other"}}}}}
+    (tmp_path / "profiles").mkdir()
+    (tmp_path / "profiles" / "traffic.json").write_text(json.dumps(d))
+    monkeypatch.setattr(bench, "ROOT", str(tmp_path))
+    monkeypatch.setattr(bench, "kernel_source_hash", lambda: h)
+    assert bench.load_traffic("w", "moments", 1) == 5
+    assert bench.load_traffic("w", "pop_x", 2) == 7
+    assert bench.load_traffic("w", "pop_x", 4) is None     # taken on other sources
+    assert bench.load_traffic("w", "pop_x", 1) is None     # plan not measured
+    assert bench.load_traffic("x", "pop_x", 2) is None
