@@ -103,6 +103,9 @@ def run_gpu(instances, precision, steps, warmup, timed_steps):
 def roofline(res, word_bytes, workload):
     cells = res["cells"]
     passes = res["passes"]
+    # a batch of several size classes launches each pass once per class: the pass's time per
+    # stage is the mean launch duration times the number of classes, its bytes those of all cells
+    nclass = res["plan"].get("size_classes", 1)
     per_pass = {}
     for name, ms in passes.items():
         if ms <= 0:
@@ -111,10 +114,11 @@ def roofline(res, word_bytes, workload):
         if name in FUSED and passes.get(FUSED[name][1], 0.0) <= 0:
             name, words = FUSED[name][0], words + ALG_WORDS[FUSED[name][1]]
         alg = words * word_bytes * cells
+        ms = ms * nclass
         per_pass[name] = dict(ms=ms, alg_bytes=alg, gbs=alg / (ms * 1e-3) / 1e9)
     dom = max(per_pass, key=lambda k: per_pass[k]["ms"])
     d = per_pass[dom]
-    traffic = load_traffic(workload, dom, res["plan"]["pops_per_block_x"])
+    traffic = load_traffic(workload, dom, res["plan"]["pops_per_block_x"]) if nclass == 1 else None
     # the same launch priced by the HBM bytes the rocprofv3 counters measured (when they were
     # taken on the current kernel sources)
     measured = None if traffic is None else traffic / (d["ms"] * 1e-3) / 1e9
@@ -122,7 +126,9 @@ def roofline(res, word_bytes, workload):
                 unit="GB/s", frac=round(d["gbs"] / HBM_PEAK_GBS, 4), traffic=traffic,
                 measured_gbs=None if measured is None else round(measured, 1),
                 measured_frac=None if measured is None else round(measured / HBM_PEAK_GBS, 4),
-                alg_bytes_per_launch=d["alg_bytes"], mean_launch_ms=round(d["ms"], 5),
+                alg_bytes_per_launch=d["alg_bytes"] if nclass == 1 else None,
+                alg_bytes_per_pass=d["alg_bytes"], launches_per_pass=nclass,
+                mean_launch_ms=round(d["ms"] / nclass, 5),
                 passes={k: dict(ms=round(v["ms"], 5), gbs=round(v["gbs"], 1)) for k, v in per_pass.items()},
                 step_frac=round(res["mlups"] * 1e6 * WORDS_PER_STEP * word_bytes / 1e9 / HBM_PEAK_GBS, 4))
 

@@ -73,3 +73,17 @@ def test_traffic_is_looked_up_for_the_plan_and_sources(tmp_path, monkeypatch):
     assert bench.load_traffic("w", "pop_x", 4) is None     # taken on other sources
     assert bench.load_traffic("w", "pop_x", 1) is None     # plan not measured
     assert bench.load_traffic("x", "pop_x", 2) is None
+
+
+def test_roofline_of_a_batch_of_several_size_classes():
+    # each pass runs once per class: per stage its time is the mean launch times the class count,
+    # its bytes those of every cell of the batch; no single-launch traffic figure applies
+    cells = 64 * 64 + 128 * 128
+    passes = {"moments": 0.002, "macro_x1": 0.004, "macro_y1": 0.0, "stress": 0.002,
+              "macro_x2": 0.003, "macro_y2": 0.0, "finalize": 0.002, "pop_x": 0.006, "pop_y": 0.005}
+    res = dict(cells=cells, passes=passes, mlups=500.0, plan=dict(pops_per_block_x=2, size_classes=2))
+    r = bench.roofline(res, 4, "quench512_fp32")
+    assert r["kernel"] == "pop_x" and r["launches_per_pass"] == 2
+    assert abs(r["achieved"] - 47 * 4 * cells / (2 * 0.006e-3) / 1e9) < 0.2
+    assert r["mean_launch_ms"] == 0.006 and r["alg_bytes_per_launch"] is None
+    assert r["traffic"] is None and r["measured_frac"] is None
