@@ -4,10 +4,12 @@ Runs only the FP64 CPU oracle (oracle/) on the seeded benchmark inputs (workload
 stores, per instance, the moments rho, ux, uy, T at a fixed random sample of cells together with
 each field's max |value| over the whole grid (the parity norm's denominators):
 
-  quench512_oracle.npz : 512x512 quench, steps 10 and 100
-  ragged64_oracle.npz  : every instance of the 64-instance ragged batch, step 50
+  quench512_oracle.npz  : 512x512 quench, steps 10 and 100
+  ragged64_oracle.npz   : every instance of the 64-instance ragged batch, step 50
+  quench2048_oracle.npz : 2048x2048 quench, step 5
 
-Usage: python tests/golden/make_oracle_samples.py [--procs N]   (about 15 minutes on 8 cores)
+Usage: python tests/golden/make_oracle_samples.py [--procs N] [--only NAME]
+(about 15 minutes on 8 cores, and 10 more for quench2048)
 """
 import argparse
 import multiprocessing as mp
@@ -29,9 +31,10 @@ def sample_cells(n_cells, k, key):
 
 
 def run_instance(args):
-    from oracle import model
+    from oracle import model, spectral
     from paper_1403_3746_amd import workloads as W
-    name, k, checkpoints, nsample = args
+    name, k, checkpoints, nsample, workers = args
+    spectral.set_workers(workers)
     insts, _ = W.config(name)
     p, ic = insts[k]
     f = model.init_equilibrium(*ic, p)
@@ -57,12 +60,14 @@ def main():
     from paper_1403_3746_amd import workloads as W
     jobs = []
     if a.only in ("", "quench512"):
-        jobs.append(("quench512", [(("quench512", 0, [10, 100], 16384))]))
+        jobs.append(("quench512", [("quench512", 0, [10, 100], 16384, a.procs)]))
+    if a.only in ("", "quench2048"):
+        jobs.append(("quench2048", [("quench2048", 0, [5], 16384, a.procs)]))
     if a.only in ("", "ragged64"):
         insts, _ = W.config("ragged64")
         # largest first so the pool finishes evenly
         order = sorted(range(len(insts)), key=lambda k: -insts[k][1][0].size)
-        jobs.append(("ragged64", [("ragged64", k, [50], 2048) for k in order]))
+        jobs.append(("ragged64", [("ragged64", k, [50], 2048, 1) for k in order]))
     for name, tasks in jobs:
         with mp.Pool(min(a.procs, len(tasks))) as pool:
             res = dict(pool.imap_unordered(run_instance, tasks))

@@ -1,9 +1,10 @@
 """GPU parity at the benchmark sizes, in the launch configuration the benchmark times.
 
 Where the oracle is too slow to run inside a test (512^2 for 100 steps, the ragged batch with
-grids up to 1024^2 for 50 steps), the HIP results are compared with oracle samples written by
-tests/golden/make_oracle_samples.py (oracle only: moments at a fixed random sample of cells plus
-each field's max |value| over the grid, the denominators of the parity norm)."""
+grids up to 1024^2 for 50 steps, 2048^2 for 5 steps), the HIP results are compared with oracle
+samples written by tests/golden/make_oracle_samples.py (oracle only: moments at a fixed random
+sample of cells plus each field's max |value| over the grid, the denominators of the parity
+norm)."""
 import os
 
 import numpy as np
@@ -116,6 +117,19 @@ def test_ragged64_fp32_every_instance_step50(torch_cuda):
         worst = max(worst, e["rho"], e["T"])
         assert e["rho"] < 1e-5 and e["T"] < 1e-5, (k, ic[0].shape, e)
     say(f"ragged64 fp32 step 50: worst rho/T error over 64 instances {worst:.2e}")
+    sim.close()
+
+
+def test_quench2048_fp32_step5_vs_oracle_samples(torch_cuda):
+    # the 2048^2 single domain in FP32, as the benchmark runs it (tuned plan, graph-replayed
+    # steps), against oracle samples at step 5: every element of the long-column y passes
+    z = _samples("quench2048")
+    (p, ic), = W.config("quench2048")[0]
+    sim = _sim([(p, ic)], "fp32")
+    sim.step(5)
+    e = _sample_errors(sim.moments(), z, "i0", 5)
+    say(f"quench2048 fp32 step 5 vs oracle samples: {e}  plan {sim.plan(0)}")
+    assert max(e.values()) < 1e-5
     sim.close()
 
 
