@@ -78,6 +78,13 @@ def test_edge_cases_rejected_on_the_host():
         lbfft.lb_init(prm, lbfft.make_dvm(dict(eta0=0.0)), lbfft.LB_FP64, [rho], [ux], [uy], [T],
                       256, 1 << 30, 0)
     assert e.value.status == lbfft.LB_E_ARG and "singular" in str(e.value)
+    # 2^a 3^b lengths with more than one factor 3 (36 = 4 * 9) are not supported line lengths
+    r36, u36, v36, t36 = W.slab(36, 36, 0.5)
+    assert lbfft.lb_workspace_bytes([lbfft.make_params(p, 36, 36)], lbfft.LB_FP64) == 0
+    with pytest.raises(lbfft.LBError) as e:
+        lbfft.lb_init([lbfft.make_params(p, 36, 36)], lbfft.make_dvm(), lbfft.LB_FP64, [r36], [u36],
+                      [v36], [t36], 256, 1 << 30, 0)
+    assert e.value.status == lbfft.LB_E_SIZE and "unsupported grid" in str(e.value)
     # calls on a null context fail cleanly
     with pytest.raises(lbfft.LBError) as e:
         lbfft.lb_set_moments(None, 0, rho, ux, uy, T)
