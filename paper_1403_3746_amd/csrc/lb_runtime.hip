@@ -16,6 +16,10 @@
 #include "lb_launch.h"
 #include "lb_types.h"
 
+#ifndef LB_GRAPH_STEPS
+#define LB_GRAPH_STEPS 16  // steps per replay of a single-class context's multi-step graph
+#endif
+
 using namespace lbfft;
 
 namespace {
@@ -181,6 +185,10 @@ struct lb_ctx {
     std::vector<Class> classes;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    // a single size class also gets a graph of graph_steps consecutive steps (fewer replays)
+    hipGraph_t graph_k = nullptr;
+    hipGraphExec_t exec_k = nullptr;
+    int graph_steps = LB_GRAPH_STEPS;
     bool use_graph = true;
     int ppb_override = 0;   // populations per x-pass block forced by LBFFT_PPB (1, 2 or 4), else tuned
     bool fuse_xy = true;    // square grids: x and y macroscopic passes in one launch (LBFFT_FUSE_XY=0: off)
@@ -587,6 +595,10 @@ lb_status lb_init(lb_ctx** out, int n_inst, const lb_params* p, const lb_dvm* dv
     c->stream = reinterpret_cast<hipStream_t>(hip_stream);
     c->lay = lay;
     if (const char* g = std::getenv("LBFFT_NO_GRAPH")) c->use_graph = !(g[0] == '1');
+    if (const char* g = std::getenv("LBFFT_GRAPH_STEPS")) {
+        const int k = std::atoi(g);
+        if (k >= 1 && k <= 64) c->graph_steps = k;
+    }
     if (const char* g = std::getenv("LBFFT_FUSE_XY")) c->fuse_xy = !(g[0] == '0');
     if (const char* g = std::getenv("LBFFT_PPB")) {
         const int v = std::atoi(g);
@@ -776,6 +788,17 @@ lb_status lb_init(lb_ctx** out, int n_inst, const lb_params* p, const lb_dvm* dv
                 if (e2 != hipSuccess) e = e2;
             }
             if (e == hipSuccess) e = hipGraphInstantiate(&c->exec, c->graph, nullptr, nullptr, 0);
+            // one size class: its steps are plain kernel sequences, so several chain in one graph
+            if (e == hipSuccess && nb == 1 && c->graph_steps > 1) {
+                e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+                if (e == hipSuccess) {
+                    hipError_t e2 = hipSuccess;
+                    for (int k = 0; e2 == hipSuccess && k < c->graph_steps; ++k) e2 = enqueue_step(*c, cs);
+                    e = hipStreamEndCapture(cs, &c->graph_k);
+                    if (e2 != hipSuccess) e = e2;
+                }
+                if (e == hipSuccess) e = hipGraphInstantiate(&c->exec_k, c->graph_k, nullptr, nullptr, 0);
+            }
         }
         for (auto x : ev)
             if (x) (void)hipEventDestroy(x);
@@ -798,7 +821,10 @@ lb_status lb_init(lb_ctx** out, int n_inst, const lb_params* p, const lb_dvm* dv
 lb_status lb_step(lb_ctx* c, int n_steps) {
     if (!c) return fail(LB_E_ARG, "null context");
     if (n_steps < 0) return fail(LB_E_ARG, "n_steps < 0");
-    for (int s = 0; s < n_steps; ++s) {
+    int s = 0;
+    if (c->exec_k)
+        for (; s + c->graph_steps <= n_steps; s += c->graph_steps) LB_HIP(hipGraphLaunch(c->exec_k, c->stream));
+    for (; s < n_steps; ++s) {
         if (c->exec) {
             LB_HIP(hipGraphLaunch(c->exec, c->stream));
         } else {
@@ -994,6 +1020,8 @@ void lb_free(lb_ctx* c) {
     if (c->stream) (void)hipStreamSynchronize(c->stream);
     if (c->exec) (void)hipGraphExecDestroy(c->exec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
+    if (c->exec_k) (void)hipGraphExecDestroy(c->exec_k);
+    if (c->graph_k) (void)hipGraphDestroy(c->graph_k);
     delete c;
 }
 

@@ -306,3 +306,20 @@ def test_step_long_columns(torch_cuda, prec):
         say(f"long columns {nx}x{ny} {prec} step 3: {errs}")
         assert max(errs.values()) < tol, (ny, nx, errs)
         sim.close()
+
+
+def test_multi_step_graph_matches_single_step_replays(torch_cuda, monkeypatch):
+    # a single size class steps through a graph of several steps while enough remain; its state
+    # must equal that of one-step replays bit for bit, history included (37 = 2 * 16 + 5)
+    p = W.base_params(hist=64)
+    ic = W.quench(64, 64, 0.9 * W.T_C, 11)
+    out = {}
+    for k in ("1", "16"):
+        monkeypatch.setenv("LBFFT_GRAPH_STEPS", k)
+        sim = _sim([(p, ic)], "fp32")
+        sim.step(37)
+        out[k] = (sim.get_f(), sim.history())
+        sim.close()
+    assert np.array_equal(out["1"][0], out["16"][0])
+    assert out["1"][1][0] == out["16"][1][0] == 0
+    assert np.array_equal(out["1"][1][1], out["16"][1][1]) and out["16"][1][1].shape == (37, 4)
