@@ -33,6 +33,9 @@
 #ifndef LB_POPX_BATCH_LDS
 #define LB_POPX_BATCH_LDS 40960  // LDS bytes up to which the x pass transforms its P lines together
 #endif
+#ifndef LB_POPX_FOLD_BASE
+#define LB_POPX_FOLD_BASE 1  // first stage: fold the base f^n into the x pass's multiplier
+#endif
 #ifndef LB_POPX_WAVES_F64
 #define LB_POPX_WAVES_F64 3  // the same for FP64 (fewer: its epilogue holds twice the registers)
 #endif
@@ -415,7 +418,7 @@ struct PopXEpi {
 #pragma unroll
             for (int f = 0; f < 7; ++f) v[j][f] = bload(a, cf[f], e, T());
 #pragma unroll
-            for (int q = 0; q < P; ++q) v[j][7 + q] = bload(a, basep[q], e, T());
+            for (int q = 0; q < P; ++q) v[j][7 + q] = has_base ? bload(a, basep[q], e, T()) : T(0);
         }
     }
     // rotu: the block's pairs are y mirrors (v_x = 0); their equilibria are those of the x-mirror
@@ -505,13 +508,17 @@ pop_x_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
     int pop[P];
 #pragma unroll
     for (int q = 0; q < P; ++q) pop[q] = D.xorder[w.job * P + q];
-    const bool has_base = st.base_field >= 0;
+    // first stage: the base is the transformed field itself, so it joins the spectral multiplier
+    // (1 - c/tau instead of -c/tau) and is not read a second time per cell
+    const bool fold = LB_POPX_FOLD_BASE && st.base_field == st.f_field;
+    const bool has_base = st.base_field >= 0 && !fold;
+    const T ct1 = fold ? ct - T(1) : ct;   // the multiplier's real part is -ct1
     const uint32_t cf[7] = {fofs<T>(I, RHO), fofs<T>(I, UX), fofs<T>(I, UY), fofs<T>(I, TT),
                             fofs<T>(I, BX), fofs<T>(I, BY), fofs<T>(I, CT)};
     uint32_t basep[P], outp[P];
 #pragma unroll
     for (int q = 0; q < P; ++q) {
-        // without a base (the bare right-hand side) the partial block is read and discarded
+        // without a base (folded, or the bare right-hand side) nothing is read for it
         basep[q] = fofs<T>(I, has_base ? st.base_field + pop[q] : F_P + pop[q]);
         // out may equal the base block (second stage writes f^{n+1} over f^n per cell)
         outp[q] = fofs<T>(I, (D.vy[pop[q]] == T(0) ? st.out_field : F_P) + pop[q]);
@@ -546,7 +553,7 @@ pop_x_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
             LineFFT<T, N, R, false>::template run_n<P>(X, lds, C::LDS, t, tws);
 #pragma unroll
             for (int q = 0; q < P; ++q) {
-                const T s = -c * D.vx[D.xorder[w.job * P + q]] * invN, mr = -ct * invN;
+                const T s = -c * D.vx[D.xorder[w.job * P + q]] * invN, mr = -ct1 * invN;
 #pragma unroll
                 for (int m = 0; m < R; ++m) {
                     const T mi = s * kv[m];
@@ -559,7 +566,7 @@ pop_x_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
 #pragma unroll
             for (int q = 0; q < P; ++q)
 #pragma unroll
-                for (int m = 0; m < R; ++m) X[q][m] = {-ct * X[q][m].re, -ct * X[q][m].im};
+                for (int m = 0; m < R; ++m) X[q][m] = {-ct1 * X[q][m].re, -ct1 * X[q][m].im};
         }
     }
 #pragma unroll
@@ -568,7 +575,7 @@ pop_x_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
         const T vx = D.vx[i];
         if (vx != T(0)) {
             LineFFT<T, N, R, false>::run(X[q], lds, t, tws);
-            const T s = -c * vx * invN, mr = -ct * invN;
+            const T s = -c * vx * invN, mr = -ct1 * invN;
 #pragma unroll
             for (int m = 0; m < R; ++m) {
                 const T mi = s * kv[m];
@@ -578,7 +585,7 @@ pop_x_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
             LineFFT<T, N, R, true>::run(X[q], lds, t, tws);
         } else {
 #pragma unroll
-            for (int m = 0; m < R; ++m) X[q][m] = {-ct * X[q][m].re, -ct * X[q][m].im};
+            for (int m = 0; m < R; ++m) X[q][m] = {-ct1 * X[q][m].re, -ct1 * X[q][m].im};
         }
     }
     if (!active) return;
