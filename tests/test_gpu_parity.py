@@ -323,3 +323,24 @@ def test_multi_step_graph_matches_single_step_replays(torch_cuda, monkeypatch):
     assert np.array_equal(out["1"][0], out["16"][0])
     assert out["1"][1][0] == out["16"][1][0] == 0
     assert np.array_equal(out["1"][1][1], out["16"][1][1]) and out["16"][1][1].shape == (37, 4)
+
+
+@pytest.mark.parametrize("ppb", ["1", "2", "4"])
+def test_full_step_every_x_pass_plan(torch_cuda, monkeypatch, ppb):
+    # two RK2 steps (both stages: base folded, then read per cell) with each x-pass plan, on grids
+    # that give its blocks one or several lines, lines of one or several waves, 4, 8 or 12
+    # elements per thread and a missing second row (ny = 1), against the oracle
+    monkeypatch.setenv("LBFFT_PPB", ppb)
+    for ny, nx in ((64, 64), (24, 128), (2, 512), (1, 96), (8, 32), (8, 1024), (8, 2048)):
+        p = W.base_params(q=-0.004, zeta=1e-3)
+        ic = W.smooth_random(nx, ny, 300 + nx + ny, T0=0.52) if ny > 2 else W.slab(nx, ny, 0.52)
+        sim = _sim([(p, ic)])
+        assert sim.plan(0)["pops_per_block_x"] == int(ppb)
+        f = model.init_equilibrium(*ic, p)
+        for _ in range(2):
+            f = model.rk2_step(f, p)
+        sim.step(2)
+        err = np.abs(sim.get_f() - f).max() / np.abs(f).max()
+        say(f"x-pass plan {ppb}, {nx}x{ny}: rel err {err:.2e}")
+        assert err < 1e-12, (ppb, nx, ny, err)
+        sim.close()
