@@ -157,9 +157,9 @@ def test_quench2048_fp32_conservation(torch_cuda):
 def test_full_length_runs_conserve(torch_cuda, name, prec):
     # the whole run of each single-domain workload (10 000 steps at 512^2, 5 000 at 2048^2):
     # finite throughout, with the FP64 grid integrals of mass and momentum drifting by at most
-    # rounding -- in FP64 ~1e-17 per step; in FP32 a systematic ~1.5e-9 per step (the equilibrium
-    # coefficients rounded to FP32 no longer sum exactly to the conserved moments), hence 5e-5
-    # over the run; the total energy is reported (the scheme conserves it only up to truncation)
+    # rounding -- in FP64 ~1e-17 per step; in FP32 a systematic ~1.5e-9 per step from rounding in
+    # the step, hence 5e-5 over the run; the total energy is reported (the scheme conserves it
+    # only up to truncation)
     insts, steps = W.config(name)
     sim = _sim(insts, prec)
     c0 = sim.conservation()
