@@ -17,7 +17,8 @@ simulation of thermal liquid-vapor system" (arXiv 1403.3746):
 
 Everything is plain NumPy/SciPy in float64 with no blocking or fusion.  Pins that tie each
 function to something other than itself live in ``tests/test_oracle_*.py``.  Parity status:
-B and C on non-trivial fields are pinned only through invariants and identities (moment
-identities of I_i, the Korteweg divergence identity, special cases); their pointwise values are
-otherwise "parity unpinned" beyond the cross-check with a naive DFT derivative.
+every function is pinned.  B, C and C_q on general non-uniform fields (T, u and rho all varying,
+H, zeta, q != 0) and the total energy e_T are pinned against the paper's formulas differentiated
+and integrated exactly (sympy) on band-limited fields, with negative controls for the plausible
+slips; the rest against closed forms, identities, special cases and a naive DFT.
 """
