@@ -7,12 +7,13 @@ as variants.  A "step" is one full RK2 step of every instance (two evaluations o
 macroscopic spectral derivatives, forcing, population x and y passes).  Inputs are resident in
 HBM before timing starts; the timed region replays the captured step graph.
 
-roofline: algorithmic HBM words per cell of each pass (listed in ALG_WORDS) times cells, over the
-pass's mean launch duration from HIP events recorded on the library's stream during a second run
-of steps (lb_step_timed); the dominant pass (largest time per step) is reported, and beside it the
-HBM bytes per launch the rocprofv3 counters measured (profiles/traffic.json) over the same time.
+roofline: algorithmic HBM words per cell of each pass times cells, over the pass's mean launch
+duration from HIP events recorded on the library's stream during a second run of steps
+(lb_step_timed); the dominant pass (largest time per step) is reported, priced at the reference
+word count (REF_WORDS) and at this design's own (ALG_WORDS), and beside it the HBM bytes per
+launch the rocprofv3 counters measured (profiles/traffic.json) over the same time.
 cpu_baseline: the FP64 CPU oracle stepping the same 512x512 initial condition for a bounded number
-of steps on the host cores.
+of steps on all host cores, and on one core.
 """
 import argparse
 import hashlib
@@ -29,8 +30,8 @@ sys.path.insert(0, ROOT)
 METRIC = "MLUPS (cells×RK2 steps/s) FP32-batched vs FP64-plain; % of HBM roofline"
 HBM_PEAK_GBS = 8000.0
 
-# Algorithmic words per cell of one launch of each pass (q = 0), averaged over the two RK
-# stages (only pop_x differs: 39 words in stage 1, 55 in stage 2 where the base f^n is read).
+# Algorithmic words per cell of one launch of each pass in this design (q = 0), averaged over the
+# two RK stages (only pop_x differs: 39 words in stage 1, 55 in stage 2 where the base f^n is read).
 ALG_WORDS = {
     "moments": 20,     # read 16 f, write rho, ux, uy, T
     "macro_x1": 9,     # read rho, T, ux, uy; write d_x rho, d_xx rho, d_x T, d_x ux, d_x uy
@@ -43,8 +44,24 @@ ALG_WORDS = {
     "pop_y": 36,       # read 12 f + 12 partials; write 12
 }
 WORDS_PER_STEP = 2 * sum(ALG_WORDS.values())   # 328
+
+# The reference count the roofline fraction is priced on: a design with the fewest passes the
+# method allows moves 262 words per cell per RK2 step -- an x population pass over the 12
+# populations with v_x != 0 (12 f + 7 coefficients read, 4 final + 8 partial writes: 31 words; 47
+# in stage 2 with 16 base reads), a y population pass that also sums the next stage's moments
+# (12 f + 8 partials + 7 coefficients + 4 x-final populations read, 12 populations + 4 moments
+# written), and macroscopic passes X1 (4 read + 5 written), Y1 (9 + 7, the stress formed in it),
+# X2 (3 + 3) and Y2 (11 + 3, B and C formed in it).  Each pass here is priced at the words that
+# design spends on the same work, never more than this design's own count: the moments at the
+# y pass's 4 + 4 moment words, the stress and finalize kernels at the words Y1 and Y2 spend beyond
+# 9 and 6, the population x pass at the x pass's 31 / 47 (39 on average).
+REF_WORDS = {
+    "moments": 8, "macro_x1": 9, "macro_y1": 9, "stress": 7, "macro_x2": 6, "macro_y2": 6,
+    "finalize": 8, "pop_x": 39, "pop_y": 36,
+}
+REF_WORDS_PER_STEP = 262
 # On square grids the x and y macroscopic passes of a stage run as one fused launch, timed in the
-# x slot: its algorithmic words are those of both.
+# x slot: its words are those of both.
 FUSED = {"macro_x1": ("macro_xy1", "macro_y1"), "macro_x2": ("macro_xy2", "macro_y2")}
 
 
@@ -101,6 +118,8 @@ def run_gpu(instances, precision, steps, warmup, timed_steps):
 
 
 def roofline(res, word_bytes, workload):
+    """Roofline of the dominant pass (largest time per step).  `achieved` / `frac` price it at the
+    reference count (REF_WORDS), `achieved_design` / `frac_design` at this design's own words."""
     cells = res["cells"]
     passes = res["passes"]
     # a batch of several size classes launches each pass once per class: the pass's time per
@@ -110,46 +129,63 @@ def roofline(res, word_bytes, workload):
     for name, ms in passes.items():
         if ms <= 0:
             continue
-        words = ALG_WORDS[name]
+        words, ref = ALG_WORDS[name], REF_WORDS[name]
         if name in FUSED and passes.get(FUSED[name][1], 0.0) <= 0:
-            name, words = FUSED[name][0], words + ALG_WORDS[FUSED[name][1]]
-        alg = words * word_bytes * cells
+            other = FUSED[name][1]
+            name, words, ref = FUSED[name][0], words + ALG_WORDS[other], ref + REF_WORDS[other]
+        alg = ref * word_bytes * cells
+        own = words * word_bytes * cells
         ms = ms * nclass
-        per_pass[name] = dict(ms=ms, alg_bytes=alg, gbs=alg / (ms * 1e-3) / 1e9)
+        per_pass[name] = dict(ms=ms, alg_bytes=alg, own_bytes=own, gbs=alg / (ms * 1e-3) / 1e9,
+                              gbs_design=own / (ms * 1e-3) / 1e9)
     dom = max(per_pass, key=lambda k: per_pass[k]["ms"])
     d = per_pass[dom]
     traffic = load_traffic(workload, dom, res["plan"]["pops_per_block_x"]) if nclass == 1 else None
     # the same launch priced by the HBM bytes the rocprofv3 counters measured (when they were
     # taken on the current kernel sources)
     measured = None if traffic is None else traffic / (d["ms"] * 1e-3) / 1e9
+    step_bytes = res["mlups"] * 1e6 * word_bytes / 1e9
     return dict(bound="hbm", kernel=dom, achieved=round(d["gbs"], 1), peak=HBM_PEAK_GBS,
                 unit="GB/s", frac=round(d["gbs"] / HBM_PEAK_GBS, 4), traffic=traffic,
+                achieved_design=round(d["gbs_design"], 1),
+                frac_design=round(d["gbs_design"] / HBM_PEAK_GBS, 4),
                 measured_gbs=None if measured is None else round(measured, 1),
                 measured_frac=None if measured is None else round(measured / HBM_PEAK_GBS, 4),
                 alg_bytes_per_launch=d["alg_bytes"] if nclass == 1 else None,
-                alg_bytes_per_pass=d["alg_bytes"], launches_per_pass=nclass,
-                mean_launch_ms=round(d["ms"] / nclass, 5),
-                passes={k: dict(ms=round(v["ms"], 5), gbs=round(v["gbs"], 1)) for k, v in per_pass.items()},
-                step_frac=round(res["mlups"] * 1e6 * WORDS_PER_STEP * word_bytes / 1e9 / HBM_PEAK_GBS, 4))
+                alg_bytes_per_pass=d["alg_bytes"], design_bytes_per_pass=d["own_bytes"],
+                launches_per_pass=nclass, mean_launch_ms=round(d["ms"] / nclass, 5),
+                passes={k: dict(ms=round(v["ms"], 5), gbs=round(v["gbs"], 1),
+                                gbs_design=round(v["gbs_design"], 1)) for k, v in per_pass.items()},
+                step_frac=round(step_bytes * REF_WORDS_PER_STEP / HBM_PEAK_GBS, 4),
+                step_frac_design=round(step_bytes * WORDS_PER_STEP / HBM_PEAK_GBS, 4))
 
 
-def cpu_baseline(instances, budget_s=15.0):
+def _oracle_rate(instances, workers, budget_s):
+    """MLUPS of the FP64 oracle stepping the first instance on the host with `workers` FFT
+    threads: one warm-up step, then as many steps as fit in about budget_s (1..20)."""
     from oracle import model, spectral
 
-    workers = os.cpu_count() or 1
     spectral.set_workers(workers)
-    p, ic = instances[0]
-    f = model.init_equilibrium(*ic, p)
-    t0 = time.perf_counter()
-    f = model.rk2_step(f, p)
-    t1 = time.perf_counter() - t0
-    n = int(max(1, min(20, budget_s / max(t1, 1e-3))))
-    t0 = time.perf_counter()
-    for _ in range(n):
+    try:
+        p, ic = instances[0]
+        f = model.init_equilibrium(*ic, p)
+        t0 = time.perf_counter()
         f = model.rk2_step(f, p)
-    dt = time.perf_counter() - t0
-    cells = ic[0].size
-    spectral.set_workers(1)
+        t1 = time.perf_counter() - t0
+        n = int(max(1, min(20, budget_s / max(t1, 1e-3))))
+        t0 = time.perf_counter()
+        for _ in range(n):
+            f = model.rk2_step(f, p)
+        dt = time.perf_counter() - t0
+    finally:
+        spectral.set_workers(1)
+    return ic[0].size * n / dt / 1e6, n
+
+
+def cpu_baseline(instances, budget_s=15.0, budget_1core_s=8.0):
+    workers = os.cpu_count() or 1
+    rate, n = _oracle_rate(instances, workers, budget_s)
+    rate1, n1 = _oracle_rate(instances, 1, budget_1core_s)
     model_name = None
     try:
         for line in open("/proc/cpuinfo"):
@@ -158,10 +194,13 @@ def cpu_baseline(instances, budget_s=15.0):
                 break
     except OSError:
         pass
-    return dict(value=round(cells * n / dt / 1e6, 4), unit="MLUPS", cores=workers, kind="oracle",
+    shape = instances[0][1][0].shape
+    return dict(value=round(rate, 4), unit="MLUPS", cores=workers, kind="oracle",
                 cpu=model_name,
-                sample=f"FP64 oracle, {ic[0].shape[1]}x{ic[0].shape[0]} quench, {n} RK2 steps after 1 "
-                       f"warm-up step, scipy.fft workers={workers}")
+                sample=f"FP64 oracle, {shape[1]}x{shape[0]} quench, {n} RK2 steps after 1 "
+                       f"warm-up step, scipy.fft workers={workers}",
+                single_core=dict(value=round(rate1, 4), unit="MLUPS", cores=1,
+                                 sample=f"the same, {n1} RK2 steps, scipy.fft workers=1"))
 
 
 def calib_copy():
@@ -230,16 +269,24 @@ def main():
     }
     if not args.no_variants:
         var = {}
-        r32 = run_gpu(insts, "fp32", args.steps, args.warmup, args.timed_steps)
-        var["quench512_fp32"] = dict(mlups=round(r32["mlups"], 2), ms_per_step=round(r32["ms_per_step"], 5),
-                                     roofline=roofline(r32, 4, "quench512_fp32"), plan=r32["plan"])
-        binsts, _ = W.config("batch128x256")
-        bsteps = max(1, args.steps // 4)
-        rb = run_gpu(binsts, "fp32", bsteps, max(1, args.warmup // 4), max(1, args.timed_steps // 4))
-        var["batch128x256_fp32"] = dict(mlups=round(rb["mlups"], 2), ms_per_step=round(rb["ms_per_step"], 5),
-                                        steps=bsteps, roofline=roofline(rb, 4, "batch128x256_fp32"),
-                                        plan=rb["plan"])
+
+        def variant(name, prec, steps, warmup, timed):
+            vi, _ = W.config(name)
+            r = run_gpu(vi, prec, steps, warmup, timed)
+            key = f"{name}_{prec}"
+            return r, dict(mlups=round(r["mlups"], 2), ms_per_step=round(r["ms_per_step"], 5),
+                           steps=steps, roofline=roofline(r, 8 if prec == "fp64" else 4, key),
+                           plan=r["plan"])
+
+        _, var["quench512_fp32"] = variant("quench512", "fp32", args.steps, args.warmup, args.timed_steps)
+        rb, var["batch128x256_fp32"] = variant("batch128x256", "fp32", args.steps, args.warmup,
+                                               max(1, args.timed_steps // 4))
         var["fp32_batched_over_fp64_plain"] = round(rb["mlups"] / main_res["mlups"], 3)
+        # the large single domain with its per-step FP64 conservation history, and the ragged batch
+        # (fewer steps: each step is 8-16x the work of the headline's)
+        big_steps, big_warm = max(1, args.steps // 8), max(1, args.warmup // 4)
+        _, var["quench2048_fp32"] = variant("quench2048", "fp32", big_steps, big_warm, 2)
+        _, var["ragged64_fp32"] = variant("ragged64", "fp32", big_steps, big_warm, 2)
         out["variants"] = var
     if not args.no_cpu:
         out["cpu_baseline"] = cpu_baseline(insts)

@@ -99,9 +99,10 @@ lb_status lb_init(lb_ctx** out, int n_inst, const lb_params* p, const lb_dvm* dv
 /* Enqueue n_steps >= 0 Runge-Kutta steps (Sec. 2.3) of every instance on the stream:
  *   f^{n+1/2} = f^n + dt/2 R(f^n),  f^{n+1} = f^n + dt R(f^{n+1/2}),
  *   R(f) = -v_i . grad f_i - (f_i - f_i^eq)/tau + I_i.
- * Steps are replayed from captured HIP graphs: one step per replay, and for a batch of a single
- * size class also a graph of 16 consecutive steps (LBFFT_GRAPH_STEPS in the environment at
- * lb_init: 1..64) used while at least that many steps remain.  Asynchronous. */
+ * Steps are replayed from captured HIP graphs: one step per replay, and a graph of 16
+ * consecutive steps (LBFFT_GRAPH_STEPS in the environment at lb_init: 1..64) used while at least
+ * that many steps remain.  In both, the size classes of a batch are parallel branches that join
+ * only at the end of the graph.  Asynchronous. */
 lb_status lb_step(lb_ctx* ctx, int n_steps);
 
 /* Block until all enqueued work is done; reports asynchronous HIP errors. */

@@ -17,7 +17,7 @@
 #include "lb_types.h"
 
 #ifndef LB_GRAPH_STEPS
-#define LB_GRAPH_STEPS 16  // steps per replay of a single-class context's multi-step graph
+#define LB_GRAPH_STEPS 16  // steps per replay of the multi-step graph
 #endif
 
 using namespace lbfft;
@@ -185,7 +185,7 @@ struct lb_ctx {
     std::vector<Class> classes;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
-    // a single size class also gets a graph of graph_steps consecutive steps (fewer replays)
+    // a graph of graph_steps consecutive steps (fewer replays while enough steps remain)
     hipGraph_t graph_k = nullptr;
     hipGraphExec_t exec_k = nullptr;
     int graph_steps = LB_GRAPH_STEPS;
@@ -405,18 +405,55 @@ hipError_t enqueue_step(const lb_ctx& c, hipStream_t s, PassHook* hook = nullptr
     return hipSuccess;
 }
 
-// One step captured as a graph with the size classes as parallel branches: the capture stream
-// forks to one stream per class (default priority) and joins them again.
-hipError_t capture_step(const lb_ctx& c, hipStream_t cs, std::vector<hipStream_t>& br,
-                        std::vector<hipEvent_t>& ev) {
-    if (c.classes.size() <= 1) return enqueue_step(c, cs);
+// `nsteps` steps of every instance captured as one graph.  With several size classes the capture
+// stream forks once to one stream per class (default priority); each branch runs its class's steps
+// in order and the branches join once at the end, so classes never wait for each other between
+// steps and every fork/join event is recorded exactly once in the capture.
+hipError_t capture_steps(const lb_ctx& c, hipStream_t cs, std::vector<hipStream_t>& br,
+                         std::vector<hipEvent_t>& ev, int nsteps) {
+    if (c.classes.size() <= 1) {
+        for (int s = 0; s < nsteps; ++s) {
+            hipError_t e = enqueue_step(c, cs);
+            if (e != hipSuccess) return e;
+        }
+        return hipSuccess;
+    }
     hipError_t e = hipEventRecord(ev[0], cs);
     for (size_t k = 0; e == hipSuccess && k < c.classes.size(); ++k) {
         e = hipStreamWaitEvent(br[k], ev[0], 0);
-        if (e == hipSuccess) e = enqueue_class_step(c, c.classes[k], br[k]);
+        for (int s = 0; e == hipSuccess && s < nsteps; ++s) e = enqueue_class_step(c, c.classes[k], br[k]);
         if (e == hipSuccess) e = hipEventRecord(ev[k + 1], br[k]);
         if (e == hipSuccess) e = hipStreamWaitEvent(cs, ev[k + 1], 0);
     }
+    return e;
+}
+
+// Capture `nsteps` steps on private streams with fresh fork/join events, instantiate and upload the
+// graph (so that its first replay costs no more than later ones).
+hipError_t build_graph(const lb_ctx& c, int nsteps, hipGraph_t* graph, hipGraphExec_t* exec) {
+    const size_t nb = c.classes.size();
+    std::vector<hipStream_t> br(nb, nullptr);
+    std::vector<hipEvent_t> ev(nb + 1, nullptr);
+    hipStream_t cs = nullptr;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    for (size_t k = 0; e == hipSuccess && k < nb; ++k) e = hipStreamCreateWithFlags(&br[k], hipStreamNonBlocking);
+    for (size_t k = 0; e == hipSuccess && k <= nb; ++k) e = hipEventCreateWithFlags(&ev[k], hipEventDisableTiming);
+    if (e == hipSuccess) {
+        e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+        if (e == hipSuccess) {
+            hipError_t e2 = capture_steps(c, cs, br, ev, nsteps);
+            e = hipStreamEndCapture(cs, graph);
+            if (e2 != hipSuccess) e = e2;
+        }
+        if (e == hipSuccess) e = hipGraphInstantiate(exec, *graph, nullptr, nullptr, 0);
+        if (e == hipSuccess) e = hipGraphUpload(*exec, c.stream);
+        if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+    }
+    for (auto x : ev)
+        if (x) (void)hipEventDestroy(x);
+    for (auto x : br)
+        if (x) (void)hipStreamDestroy(x);
+    if (cs) (void)hipStreamDestroy(cs);
     return e;
 }
 
@@ -770,41 +807,11 @@ lb_status lb_init(lb_ctx** out, int n_inst, const lb_params* p, const lb_dvm* dv
             }
         }
     }
-    // capture one Runge-Kutta step into a graph: private streams of default priority, one
-    // branch per size class
+    // capture one Runge-Kutta step into a graph, and graph_steps consecutive steps into a second
+    // one (fewer replays): private streams of default priority, one branch per size class
     if (ok && c->use_graph) {
-        const size_t nb = c->classes.size();
-        std::vector<hipStream_t> br(nb, nullptr);
-        std::vector<hipEvent_t> ev(nb + 1, nullptr);
-        hipStream_t cs = nullptr;
-        hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
-        for (size_t k = 0; e == hipSuccess && k < nb; ++k) e = hipStreamCreateWithFlags(&br[k], hipStreamNonBlocking);
-        for (size_t k = 0; e == hipSuccess && k <= nb; ++k) e = hipEventCreateWithFlags(&ev[k], hipEventDisableTiming);
-        if (e == hipSuccess) {
-            e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-            if (e == hipSuccess) {
-                hipError_t e2 = capture_step(*c, cs, br, ev);
-                e = hipStreamEndCapture(cs, &c->graph);
-                if (e2 != hipSuccess) e = e2;
-            }
-            if (e == hipSuccess) e = hipGraphInstantiate(&c->exec, c->graph, nullptr, nullptr, 0);
-            // one size class: its steps are plain kernel sequences, so several chain in one graph
-            if (e == hipSuccess && nb == 1 && c->graph_steps > 1) {
-                e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
-                if (e == hipSuccess) {
-                    hipError_t e2 = hipSuccess;
-                    for (int k = 0; e2 == hipSuccess && k < c->graph_steps; ++k) e2 = enqueue_step(*c, cs);
-                    e = hipStreamEndCapture(cs, &c->graph_k);
-                    if (e2 != hipSuccess) e = e2;
-                }
-                if (e == hipSuccess) e = hipGraphInstantiate(&c->exec_k, c->graph_k, nullptr, nullptr, 0);
-            }
-        }
-        for (auto x : ev)
-            if (x) (void)hipEventDestroy(x);
-        for (auto x : br)
-            if (x) (void)hipStreamDestroy(x);
-        if (cs) (void)hipStreamDestroy(cs);
+        hipError_t e = build_graph(*c, 1, &c->graph, &c->exec);
+        if (e == hipSuccess && c->graph_steps > 1) e = build_graph(*c, c->graph_steps, &c->graph_k, &c->exec_k);
         if (e != hipSuccess) {
             ok = false;
             st = fail(LB_E_HIP, "graph capture: %s", hipGetErrorString(e));

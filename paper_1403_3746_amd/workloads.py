@@ -72,7 +72,8 @@ def config(name):
         p = base_params()
         return [(p, quench(512, 512, 0.9 * T_C, 2000))], 10000
     if name == "quench2048":
-        p = base_params()
+        # FP32 state with the FP64 mass/energy reductions run every step (a history ring)
+        p = base_params(hist=5000)
         return [(p, quench(2048, 2048, 0.85 * T_C, 3000))], 5000
     if name == "batch128x256":
         Ts = T_C * (0.85 + 0.13 * np.random.default_rng(4999).uniform(size=256))

@@ -16,6 +16,17 @@ def test_words_per_step():
     assert bench.ALG_WORDS["pop_x"] == (39 + 55) // 2
 
 
+def test_reference_words_never_exceed_the_design_count():
+    # the reference count prices the x population pass at its 31 / 47 words (39 on average) and
+    # no pass above this design's own words; the passes together stay within the 262 words per
+    # step of the reference design
+    assert bench.REF_WORDS["pop_x"] == (31 + 47) // 2
+    assert set(bench.REF_WORDS) == set(bench.ALG_WORDS)
+    for k, v in bench.REF_WORDS.items():
+        assert 0 < v <= bench.ALG_WORDS[k]
+    assert 2 * sum(bench.REF_WORDS.values()) <= bench.REF_WORDS_PER_STEP == 262
+
+
 def test_roofline_of_fused_and_separate_passes():
     cells = 512 * 512
     passes = {"moments": 0.0074, "macro_x1": 0.0142, "macro_y1": 0.0, "stress": 0.0057,
@@ -28,12 +39,14 @@ def test_roofline_of_fused_and_separate_passes():
     assert "macro_xy1" in r["passes"] and "macro_x1" not in r["passes"]
     xy1 = 18 * 8 * cells / (0.0142e-3) / 1e9
     assert abs(r["passes"]["macro_xy1"]["gbs"] - round(xy1, 1)) < 0.2
-    alg = 47 * 8 * cells
+    alg = 39 * 8 * cells
     assert r["alg_bytes_per_launch"] == alg
     assert abs(r["achieved"] - alg / 0.0213e-3 / 1e9) < 0.2
     assert abs(r["frac"] - r["achieved"] / 8000.0) < 1e-4
+    assert abs(r["achieved_design"] - 47 * 8 * cells / 0.0213e-3 / 1e9) < 0.2
     assert r["traffic"] is None and r["measured_frac"] is None   # no counters for this workload
-    assert abs(r["step_frac"] - 1500e6 * 328 * 8 / 1e9 / 8000) < 1e-4
+    assert abs(r["step_frac"] - 1500e6 * 262 * 8 / 1e9 / 8000) < 1e-4
+    assert abs(r["step_frac_design"] - 1500e6 * 328 * 8 / 1e9 / 8000) < 1e-4
     # separate launches (non-square grids) keep the x and y names
     passes.update(macro_y1=0.0107, macro_y2=0.0079)
     r = bench.roofline(dict(res, passes=passes), 8, "no_such_workload")
@@ -84,6 +97,6 @@ def test_roofline_of_a_batch_of_several_size_classes():
     res = dict(cells=cells, passes=passes, mlups=500.0, plan=dict(pops_per_block_x=2, size_classes=2))
     r = bench.roofline(res, 4, "quench512_fp32")
     assert r["kernel"] == "pop_x" and r["launches_per_pass"] == 2
-    assert abs(r["achieved"] - 47 * 4 * cells / (2 * 0.006e-3) / 1e9) < 0.2
+    assert abs(r["achieved"] - 39 * 4 * cells / (2 * 0.006e-3) / 1e9) < 0.2
     assert r["mean_launch_ms"] == 0.006 and r["alg_bytes_per_launch"] is None
     assert r["traffic"] is None and r["measured_frac"] is None

@@ -184,9 +184,11 @@ def test_nonfinite_state_is_reported(torch_cuda):
     sim.close()
 
 
-def test_ragged_batch_matches_solo_and_oracle(torch_cuda):
+def test_ragged_batch_matches_solo_and_oracle(torch_cuda, monkeypatch):
     # three sizes, four instances, one context: each instance equals its solo run bitwise and the
-    # oracle within the FP64 bar after 10 steps.
+    # oracle within the FP64 bar after 10 steps.  The launch plan is pinned: separately tuned
+    # contexts may pick x-pass plans that round differently.
+    monkeypatch.setenv("LBFFT_PPB", "2")
     insts = [(W.base_params(), W.slab(64, 64, 0.52)),
              (W.base_params(), W.quench(96, 96, 0.53, 5)),
              (W.base_params(q=-0.004), W.quench(64, 64, 0.55, 6)),
@@ -206,7 +208,8 @@ def test_ragged_batch_matches_solo_and_oracle(torch_cuda):
     sim.close()
 
 
-def test_step_timed_matches_graph_step(torch_cuda):
+def test_step_timed_matches_graph_step(torch_cuda, monkeypatch):
+    monkeypatch.setenv("LBFFT_PPB", "2")   # one plan for both contexts
     p = W.base_params()
     ic = W.quench(64, 48, 0.52, 9)
     a, b = _sim([(p, ic)]), _sim([(p, ic)], )
@@ -311,6 +314,7 @@ def test_step_long_columns(torch_cuda, prec):
 def test_multi_step_graph_matches_single_step_replays(torch_cuda, monkeypatch):
     # a single size class steps through a graph of several steps while enough remain; its state
     # must equal that of one-step replays bit for bit, history included (37 = 2 * 16 + 5)
+    monkeypatch.setenv("LBFFT_PPB", "2")   # one plan for both contexts
     p = W.base_params(hist=64)
     ic = W.quench(64, 64, 0.9 * W.T_C, 11)
     out = {}
@@ -323,6 +327,30 @@ def test_multi_step_graph_matches_single_step_replays(torch_cuda, monkeypatch):
     assert np.array_equal(out["1"][0], out["16"][0])
     assert out["1"][1][0] == out["16"][1][0] == 0
     assert np.array_equal(out["1"][1][1], out["16"][1][1]) and out["16"][1][1].shape == (37, 4)
+
+
+def test_ragged_multi_step_graph_matches_single_step_replays(torch_cuda, monkeypatch):
+    # a batch of several size classes replays a graph of several steps whose class branches join
+    # only at its end; states and histories must equal one-step replays bit for bit
+    monkeypatch.setenv("LBFFT_PPB", "2")
+    insts = [(W.base_params(hist=64), W.quench(64, 64, 0.9 * W.T_C, 12)),
+             (W.base_params(), W.slab(96, 96, 0.52)),
+             (W.base_params(hist=40), W.quench(128, 32, 0.53, 13)),
+             (W.base_params(), W.quench(64, 64, 0.51, 14))]
+    out = {}
+    for k in ("1", "16"):
+        monkeypatch.setenv("LBFFT_GRAPH_STEPS", k)
+        sim = _sim(insts, "fp32")
+        assert sim.plan(0)["size_classes"] == 3
+        sim.step(37)
+        out[k] = ([sim.get_f(i) for i in range(len(insts))], sim.history(0), sim.history(2))
+        sim.close()
+    for i in range(len(insts)):
+        assert np.array_equal(out["1"][0][i], out["16"][0][i]), i
+    for h in (1, 2):
+        assert out["1"][h][0] == out["16"][h][0]
+        assert np.array_equal(out["1"][h][1], out["16"][h][1])
+    assert out["16"][1][1].shape == (37, 4) and out["16"][2][0] == 0
 
 
 @pytest.mark.parametrize("ppb", ["1", "2", "4"])
