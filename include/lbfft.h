@@ -129,7 +129,10 @@ lb_status lb_conservation_history(lb_ctx* ctx, int inst, int max_entries, double
                                   long long* first_step);
 
 /* Copy the populations of instance inst to / from a host float64 array [16][ny][nx]
- * (checkpoint and restart; in FP32 mode lb_set_f rounds to float32).  Synchronise. */
+ * (checkpoint and restart).  In FP32 mode the device holds the deviation f - fref from a fixed
+ * reference equilibrium (at rest, the mean initial density and temperature; float64), so that its
+ * rounding scales with the deviation instead of f: lb_get_f returns fref + the float32 deviation,
+ * lb_set_f stores the deviation rounded to float32.  Synchronise. */
 lb_status lb_get_f(lb_ctx* ctx, int inst, double* f);
 lb_status lb_set_f(lb_ctx* ctx, int inst, const double* f);
 
@@ -177,9 +180,14 @@ enum {
  * lb_step.  For measurement only. */
 lb_status lb_step_timed(lb_ctx* ctx, int n_steps, double ms[LB_NPASS]);
 
-/* Launch plan chosen for instance inst's size class at lb_init (measured on the instance's
- * data unless the environment sets LBFFT_TUNE=0):  out[0] = populations per block of the x
- * population pass (1, 2 or 4), out[1] = size classes in the context.  n = length of out (>= 2). */
+/* Launch plan chosen for instance inst's size class at lb_init (measured on the class's data
+ * unless the environment sets LBFFT_TUNE=0; LBFFT_PPB and LBFFT_YWIDE fix a choice):
+ *  out[0] = populations per block of the x population pass (1, 2 or 4),
+ *  out[1] = size classes in the context,
+ *  out[2] = 1 if the population y pass runs the wide y tiles (blocks of up to 1024 threads,
+ *           twice the column pairs of long columns), else 0.  The wide tiles exist in FP32 for y
+ *           lines long enough to be limited by the default 512-thread block; elsewhere out[2] = 0.
+ * n = length of out (>= 2; entries beyond min(n, 3) are not written). */
 lb_status lb_plan_info(lb_ctx* ctx, int inst, int* out, int n);
 
 /* Release the context (not the caller's workspace).  NULL is ignored. */

@@ -268,18 +268,18 @@ struct TwSet {
     twptr<T> table;
     int t;
 
-    template <int s>
-    __device__ __forceinline__ void fetch(int b, cpx<T>* d) const {
-        constexpr int r = P.r[s], Ns = plan_ns(P, s);
-        tw_fetch<T, r>(table, ((t + b * TPL) % Ns) * (N / (Ns * r)), d);
-    }
+    // pass s's twiddles, read with the index the pass itself uses (stockham_pass)
     template <int s>
     __device__ __forceinline__ void load_pass() {
         if constexpr (s < P.np) {
             constexpr int r = P.r[s], Ns = plan_ns(P, s), NB = R / r, OFF = offset(s);
             if constexpr (Ns > 1) {
 #pragma unroll
-                for (int b = 0; b < NB; ++b) fetch<s>(b, w + OFF + b * tw_reads(r));
+                for (int b = 0; b < NB; ++b) {
+                    const int j = t + b * TPL;
+                    const int k = j % Ns;
+                    tw_fetch<T, r>(table, k * (N / (Ns * r)), w + OFF + b * tw_reads(r));
+                }
             }
             load_pass<s + 1>();
         }

@@ -16,6 +16,8 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include <type_traits>
+
 #include "lb_decode.h"
 #include "lb_fft.h"
 #include "lb_types.h"
@@ -26,9 +28,12 @@
 #ifndef LB_YMAX_THREADS
 #define LB_YMAX_THREADS 512  // threads per y-pass block at most
 #endif
+#ifndef LB_YMAX_THREADS_WIDE
+#define LB_YMAX_THREADS_WIDE 1024  // the same for the wide y-tile variant the tuner may pick
+#endif
 #define LB_LDS_BYTES 163840      // LDS of one CU
 #ifndef LB_POPX_WAVES
-#define LB_POPX_WAVES 4  // waves per SIMD the single-population FP32 x pass must fit (register budget)
+#define LB_POPX_WAVES 3  // waves per SIMD the single-population FP32 x pass must fit (register budget)
 #endif
 #ifndef LB_POPX_BATCH_LDS
 #define LB_POPX_BATCH_LDS 40960  // LDS bytes up to which the x pass transforms its P lines together
@@ -38,6 +43,9 @@
 #endif
 #ifndef LB_POPX_WAVES_F64
 #define LB_POPX_WAVES_F64 3  // the same for FP64 (fewer: its epilogue holds twice the registers)
+#endif
+#ifndef LB_FP32_EQ64
+#define LB_FP32_EQ64 1   // FP32 state: form the equilibrium in float64 arithmetic (see EqType)
 #endif
 
 namespace lbfft {
@@ -49,7 +57,7 @@ namespace lbfft {
 // from L2.
 // LDS: x blocks (lanes of one line adjacent) store each line contiguously; y blocks (lanes of
 // neighbouring lines adjacent) interleave their lines word by word (LS = LPW).
-template <typename T, int N, int DIR, int LPW_OVERRIDE = 0>
+template <typename T, int N, int DIR, int LPW_OVERRIDE = 0, int MAXT = LB_YMAX_THREADS>
 struct LineCfg {
     static constexpr int R = default_R(N);
     static constexpr int TPL = N / R;
@@ -57,11 +65,11 @@ struct LineCfg {
     static constexpr int at_least(int l, int lo) { return l < lo ? lo : l; }
     // x: one line per block unless lines are short (then fill one wave)
     static constexpr int lpw_x() { return at_least(64 / TPL, 1); }
-    // y: LB_YSEG-byte row segments, at least one wave per block, at most LB_YMAX_THREADS threads
-    // and the LDS of one CU (long lines get fewer column pairs)
+    // y: LB_YSEG-byte row segments, at least one wave per block, at most MAXT threads and the
+    // LDS of one CU (long lines get fewer column pairs)
     static constexpr int lpw_y() {
         int l = at_least(at_least(LB_YSEG / CB, 64 / TPL), 1);
-        while (l > 1 && (l * TPL > LB_YMAX_THREADS || l * lds_line(N) * CB > LB_LDS_BYTES)) l /= 2;
+        while (l > 1 && (l * TPL > MAXT || l * lds_line(N) * CB > LB_LDS_BYTES)) l /= 2;
         return l;
     }
     static constexpr int LPW = LPW_OVERRIDE > 0 ? LPW_OVERRIDE : (DIR == 0 ? lpw_x() : lpw_y());
@@ -71,6 +79,16 @@ struct LineCfg {
     // LDS base of line l of the block
     __device__ __forceinline__ static int lds_base(int l) { return DIR == 0 ? l * lds_line(N) : l; }
 };
+
+// The wide y-tile variant of the population y pass (blocks of up to LB_YMAX_THREADS_WIDE threads)
+// exists where it holds more column pairs than the default one for lines of N points, and in FP32
+// only: a 1024-thread block leaves 128 registers per thread, which the FP64 pass (and the
+// macroscopic passes in either precision) exceed -- they would spill.
+template <typename T, int N>
+constexpr bool pop_y_wide_exists() {
+    return sizeof(T) == 4 &&
+           LineCfg<T, N, 1, 0, LB_YMAX_THREADS_WIDE>::LPW != LineCfg<T, N, 1, 0, LB_YMAX_THREADS>::LPW;
+}
 
 __device__ __forceinline__ BlockWork decode_block(int ngroups, int ntiles, int njobs) {
     return decode_block_at(blockIdx.x, ngroups, ntiles, njobs);
@@ -204,8 +222,20 @@ struct Wavenum {
 };
 
 // ---------------------------------------------------------------------------------------
-// Macroscopic line pass driven by a job table: the work of block b (LPW lines per block).
-template <typename T, int N, int DIR, int LPW_>
+// Macroscopic line pass driven by a job table: the work of block b (LPW lines per block, Q jobs
+// of the job table per block).  With Q > 1 the lines of all Q jobs are requested before the first
+// transform, so the later jobs' loads (and the earlier jobs' stores) overlap the transforms.
+#ifndef LB_MACRO_JOBS_F64
+#define LB_MACRO_JOBS_F64 1   // jobs per block of the FP64 macroscopic line passes
+#endif
+#ifndef LB_MACRO_JOBS_F32
+#define LB_MACRO_JOBS_F32 1   // the same in FP32
+#endif
+template <typename T>
+__host__ __device__ constexpr int macro_jobs() { return sizeof(T) == 8 ? LB_MACRO_JOBS_F64 : LB_MACRO_JOBS_F32; }
+__host__ __device__ constexpr int job_slots(int njobs, int Q) { return (njobs + Q - 1) / Q; }
+
+template <typename T, int N, int DIR, int LPW_, int Q = macro_jobs<T>()>
 __device__ __forceinline__ void macro_body(int b, const InstDesc* __restrict__ insts,
                                            const int* __restrict__ ilist, int ngroups, int ntiles,
                                            const JobDesc* __restrict__ jobs, int njobs,
@@ -217,11 +247,24 @@ __device__ __forceinline__ void macro_body(int b, const InstDesc* __restrict__ i
     using IFFT = LineFFT<T, N, C::R, true, C::LS, WAVE>;
     constexpr int R = C::R, TPL = C::TPL, LPW = C::LPW;
     constexpr bool JM = DIR == 0 ? LB_JOBMAJOR_X : LB_JOBMAJOR_Y;
-    const BlockWork w = JM ? decode_block_jm(b, ngroups, ntiles, njobs) : decode_block_at(b, ngroups, ntiles, njobs);
+    const int nslots = job_slots(njobs, Q);
+    const BlockWork w = JM ? decode_block_jm(b, ngroups, ntiles, nslots) : decode_block_at(b, ngroups, ntiles, nslots);
     if (!w.valid) return;
     const InstDesc& I = insts[ilist[w.inst_local]];
-    const JobDesc J = jobs[w.job];
-    if (J.flag_q && I.q == 0.0) return;
+    // the block's jobs (uniform over the block): a slot past the table's end, or a q-flux job of
+    // an instance with q = 0, does nothing
+    JobDesc J[Q];
+    bool run[Q];
+    bool any = false;
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        const int jq = w.job * Q + q;
+        run[q] = jq < njobs;
+        J[q] = jobs[run[q] ? jq : 0];
+        if (J[q].flag_q && I.q == 0.0) run[q] = false;
+        any = any || run[q];
+    }
+    if (!any) return;
 
     const int tid = threadIdx.x;
     const int l = DIR == 0 ? tid / TPL : tid % LPW;
@@ -234,45 +277,51 @@ __device__ __forceinline__ void macro_body(int b, const InstDesc* __restrict__ i
     const LB_GLOBAL T* kap = gcast(reinterpret_cast<const T*>(DIR == 0 ? I.kx : I.ky));
     const twptr<T> tw = gcast(reinterpret_cast<const cpx<T>*>(DIR == 0 ? I.twx : I.twy));
 
-    cpx<T> X[R], Y[R];
-    load_line<T, DIR, R, TPL>(fieldp<T>(I, J.in), X, line, t, nx, ny, active);
-    // twiddles and wavenumbers are shared by the forward and both inverse transforms
+    cpx<T> X[Q][R], Y[R];
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+        if (run[q]) load_line<T, DIR, R, TPL>(fieldp<T>(I, J[q].in), X[q], line, t, nx, ny, active);
+    // twiddles and wavenumbers are shared by the forward and inverse transforms of every job
     typename FFT::Tw tws;
     tws.load(tw, t);
     Wavenum<T, R, TPL> kv;
     kv.load(kap, t);
-    FFT::run(X, lds, t, tws);
     const T invN = T(1.0 / N);
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+        if (!run[q]) continue;
+        FFT::run(X[q], lds, t, tws);
 #pragma unroll 1
-    for (int o = 0; o < 2; ++o) {
-        // select the job slot without runtime indexing (which would go through scratch)
-        const int outf = o == 0 ? J.out[0] : J.out[1];
-        if (outf < 0) continue;
-        const int mk = o == 0 ? J.mult[0] : J.mult[1];
-        // one uniform branch per output, outside the element loop
-        if (mk == M_D) {
+        for (int o = 0; o < 2; ++o) {
+            // select the job slot without runtime indexing (which would go through scratch)
+            const int outf = o == 0 ? J[q].out[0] : J[q].out[1];
+            if (outf < 0) continue;
+            const int mk = o == 0 ? J[q].mult[0] : J[q].mult[1];
+            // one uniform branch per output, outside the element loop
+            if (mk == M_D) {
 #pragma unroll
-            for (int m = 0; m < R; ++m) Y[m] = spectral_mult<M_D>(kv[m], invN, X[m]);
-        } else if (mk == M_DD) {
+                for (int m = 0; m < R; ++m) Y[m] = spectral_mult<M_D>(kv[m], invN, X[q][m]);
+            } else if (mk == M_DD) {
 #pragma unroll
-            for (int m = 0; m < R; ++m) Y[m] = spectral_mult<M_DD>(kv[m], invN, X[m]);
-        } else {
-#pragma unroll
-            for (int m = 0; m < R; ++m) Y[m] = spectral_mult<M_NONE>(kv[m], invN, X[m]);
-        }
-        IFFT::run(Y, lds, t, tws);
-        if (!active) continue;
-        LB_GLOBAL T* out = fieldp<T>(I, outf);
-#pragma unroll
-        for (int m = 0; m < R; ++m) {
-            const int p = t + m * TPL;
-            if constexpr (DIR == 0) {
-                out[LineAddr<0>::re(line, p, nx)] = Y[m].re;
-                if (2 * line + 1 < ny) out[LineAddr<0>::im(line, p, nx)] = Y[m].im;
+                for (int m = 0; m < R; ++m) Y[m] = spectral_mult<M_DD>(kv[m], invN, X[q][m]);
             } else {
-                LB_GLOBAL vec2<T>* o2 = reinterpret_cast<LB_GLOBAL vec2<T>*>(out + LineAddr<1>::re(line, p, nx));
-                o2->a = Y[m].re;
-                o2->b = Y[m].im;
+#pragma unroll
+                for (int m = 0; m < R; ++m) Y[m] = spectral_mult<M_NONE>(kv[m], invN, X[q][m]);
+            }
+            IFFT::run(Y, lds, t, tws);
+            if (!active) continue;
+            LB_GLOBAL T* out = fieldp<T>(I, outf);
+#pragma unroll
+            for (int m = 0; m < R; ++m) {
+                const int p = t + m * TPL;
+                if constexpr (DIR == 0) {
+                    out[LineAddr<0>::re(line, p, nx)] = Y[m].re;
+                    if (2 * line + 1 < ny) out[LineAddr<0>::im(line, p, nx)] = Y[m].im;
+                } else {
+                    LB_GLOBAL vec2<T>* o2 = reinterpret_cast<LB_GLOBAL vec2<T>*>(out + LineAddr<1>::re(line, p, nx));
+                    o2->a = Y[m].re;
+                    o2->b = Y[m].im;
+                }
             }
         }
     }
@@ -304,15 +353,41 @@ __global__ void __launch_bounds__((MacroXY<T, N>::WG))
 macro_xy_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, int nbx,
               int ngroups_x, int ntiles_x, const JobDesc* __restrict__ jobs_x, int njobs_x,
               int ngroups_y, int ntiles_y, const JobDesc* __restrict__ jobs_y, int njobs_y) {
-    __shared__ cpx<T> lds_all[MacroXY<T, N>::LDS];
+    using M = MacroXY<T, N>;
+    __shared__ cpx<T> lds_all[M::LDS];
     const int b = blockIdx.x;
     if (b < nbx)
-        macro_body<T, N, 0, MacroXY<T, N>::LPW>(b, insts, ilist, ngroups_x, ntiles_x, jobs_x, njobs_x, lds_all);
+        macro_body<T, N, 0, M::LPW>(b, insts, ilist, ngroups_x, ntiles_x, jobs_x, njobs_x, lds_all);
     else
-        macro_body<T, N, 1, MacroXY<T, N>::LPW>(b - nbx, insts, ilist, ngroups_y, ntiles_y, jobs_y, njobs_y, lds_all);
+        macro_body<T, N, 1, M::LPW>(b - nbx, insts, ilist, ngroups_y, ntiles_y, jobs_y, njobs_y, lds_all);
 }
 
 // ---------------------------------------------------------------------------------------
+// Arithmetic type of the equilibrium in the population x pass.  With an FP32 state it is float64:
+// in a nearly uniform state every cell rounds the same FP32 dot products of the same moments the
+// same way, so their rounding (and that of the FP32 inverse moment matrix, whose columns then do
+// not sum to the exact mass row) does not average out but biases sum_i f_i^eq against rho in every
+// cell alike -- a systematic mass drift of ~1e-9 per step.  float64 FMAs issue at the float32 rate
+// here (packed FP32 is not used), and the result is rounded once.
+template <typename T>
+struct EqType {
+    using type = T;
+};
+template <>
+struct EqType<float> {
+    using type = typename std::conditional<LB_FP32_EQ64 != 0, double, float>::type;
+};
+template <typename T>
+using EqT = typename EqType<T>::type;
+
+template <typename T>
+__device__ __forceinline__ const DvmConst<EqT<T>>& eq_table(const DvmConst<T>* d, const DvmConst<double>* d64) {
+    if constexpr (std::is_same<EqT<T>, T>::value)
+        return *d;
+    else
+        return *d64;
+}
+
 // Equilibrium f_i^eq of the seven kinetic moments: f^eq = C^{-1} M^eq(rho, u, T).
 // meq_unit fills m[j] = M^eq_j / rho (the Maxwellian moments per unit density, Sec. 2.2).
 template <typename T>
@@ -383,6 +458,9 @@ __device__ __forceinline__ T feq_pop(const DvmConst<T>& D, int i, T rho, T ux, T
 #ifndef LB_EPI_EARLY_F64
 #define LB_EPI_EARLY_F64 1
 #endif
+#ifndef LB_EPI_EARLY_F32
+#define LB_EPI_EARLY_F32 0
+#endif
 #ifndef LB_EPI_CELLS_F64
 #define LB_EPI_CELLS_F64 2
 #endif
@@ -391,11 +469,13 @@ __device__ __forceinline__ T feq_pop(const DvmConst<T>& D, int i, T rho, T ux, T
 #endif
 template <typename T, int R, int TPL, int P>
 struct PopXEpi {
+    using E = EqT<T>;
     static constexpr int NV = 7 + P;   // values read per cell
     static constexpr int G = sizeof(T) == 8 ? LB_EPI_CELLS_F64 : LB_EPI_CELLS_F32;
     static constexpr int NG = 2 * R / G;
     static_assert((2 * R) % G == 0, "cells per group must divide the cells per thread");
     const DvmConst<T>& D;
+    const DvmConst<E>& DE;        // the inverse moment matrix in the equilibrium's arithmetic
     const int (&pop)[P];
     Arena a;
     const uint32_t (&cf)[7];      // field offsets of rho, u_x, u_y, T, B_x, B_y, C
@@ -404,7 +484,9 @@ struct PopXEpi {
     bool has_base;
     int line, t, nx;
     bool row1;   // the block's second row exists (odd ny leaves the last pair with one row)
-    T b, c, inv_tau;
+    E b;
+    T c, ct;     // c = alpha dt; ct = c / tau, the same value as in the spectral loss term
+    const E (&fref)[P];   // reference populations of the block's P populations (the state is f - fref)
 
     __device__ __forceinline__ uint32_t cell(int k) const {
         const int m = k >> 1, h = k & 1;
@@ -433,29 +515,35 @@ struct PopXEpi {
                 const int k = g * G + j, m = k >> 1, h = k & 1;
                 const T* x = v[g & 1][j];
                 const T rho = x[0], ux = x[1], uy = x[2], Tm = x[3], Bx = x[4], By = x[5], Dc = x[6];
-                T mq[16];
+                E mq[16];
                 // BGK gain and forcing: f^eq/tau + I = f^eq [1/tau - A - B.(v - u) - D |v - u|^2]
-                // with A = -2 D T; expanded in v: h0 + hx v_x + hy v_y + hv |v|^2.
-                const T h0 = inv_tau + T(2) * Dc * Tm + Bx * ux + By * uy - Dc * (ux * ux + uy * uy);
+                // with A = -2 D T; the force part expanded in v: h0 + hx v_x + hy v_y + hv |v|^2.
+                // The gain's 1/tau part is applied with the coefficient ct of the loss term
+                // -(c/tau) f in the spectral multiplier, so that the two cancel in the mass.
+                const T h0 = T(2) * Dc * Tm + Bx * ux + By * uy - Dc * (ux * ux + uy * uy);
                 const T hx = T(2) * Dc * ux - Bx, hy = T(2) * Dc * uy - By, hv = -Dc;
-                T fe[P];
+                E fe[P];
                 if constexpr (P == 1) {
-                    meq_unit(ux, uy, Tm, b, mq);
-                    fe[0] = feq_dot(D, pop[0], rho, mq);
+                    meq_unit<E>(E(ux), E(uy), E(Tm), b, mq);
+                    fe[0] = feq_dot(DE, pop[0], E(rho), mq);
                 } else {
-                    meq_unit(rotu ? uy : ux, rotu ? -ux : uy, Tm, b, mq);
+                    meq_unit<E>(E(rotu ? uy : ux), E(rotu ? -ux : uy), E(Tm), b, mq);
 #pragma unroll
                     for (int q = 0; q < P; q += 2)
-                        feq_mirror_pair<T, 0>(D, rotu ? D.rot[pop[q]] : pop[q], rho, mq, fe[q], fe[q + 1]);
+                        feq_mirror_pair<E, 0>(DE, rotu ? D.rot[pop[q]] : pop[q], E(rho), mq, fe[q], fe[q + 1]);
                 }
                 const uint32_t e = cell(k);
 #pragma unroll
                 for (int q = 0; q < P; ++q) {
                     const int i = pop[q];
+                    // relaxation towards f^eq of the deviation from the reference: the loss of
+                    // the reference itself, -ct fref, joins the gain ct f^eq
+                    const T feq = T(fe[q]);
+                    const T dfeq = T(fe[q] - fref[q]);
                     const T gq = h0 + hx * D.vx[i] + hy * D.vy[i] + hv * (D.w[i] - D.eta2[i]);
                     const T lin = h == 0 ? X[q][m].re : X[q][m].im;
                     const T base = has_base ? x[7 + q] : T(0);
-                    const T out = base + lin + c * (fe[q] * gq);
+                    const T out = base + lin + ct * dfeq + c * (feq * gq);
                     if (h == 0 || row1) bstore(a, outp[q], e, out);
                 }
             }
@@ -475,14 +563,17 @@ constexpr int popx_waves(int N, int P) {
 // Population x pass: one block = (instance, tile of row pairs, P populations).  For each
 // population i of the block (D.xorder[job*P + q]):
 //   out = base + c [ -v_x D_x f - (f - f^eq)/tau + I ]
-// to out_field + i if v_y = 0 (final) or to the partial block F_P + i otherwise.  The terms
-// linear in f, -c v_x D_x f - (c/tau) f, are one spectral multiplier (-c/tau + i (-c v_x k))/N;
-// the equilibrium moments and the coefficient loads of a cell are shared by the P populations.
+// to out_field + i if v_y = 0 (final) or to the partial block F_P + i otherwise.  Fields hold
+// g = f - fref with fref uniform, so D_x f = D_x g and the terms linear in g, -c v_x D_x g -
+// (c/tau) g, are one spectral multiplier (-c/tau + i (-c v_x k))/N, while the reference's own loss
+// -(c/tau) fref joins the gain: (c/tau)(f^eq - fref).  The equilibrium moments and the coefficient
+// loads of a cell are shared by the P populations.
 template <typename T, int N, int P>
 __global__ void __launch_bounds__((LineCfg<T, N, 0>::WG))
 __attribute__((amdgpu_waves_per_eu(popx_waves<T>(N, P))))
 pop_x_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, int ngroups,
-           int ntiles, const DvmConst<T>* __restrict__ dvm, StageArgs st) {
+           int ntiles, const DvmConst<T>* __restrict__ dvm, const DvmConst<double>* __restrict__ dvm64,
+           StageArgs st) {
     using C = LineCfg<T, N, 0>;
     constexpr int R = C::R, TPL = C::TPL;
     // the block's P lines are transformed together when their LDS fits the budget
@@ -524,13 +615,16 @@ pop_x_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
         outp[q] = fofs<T>(I, (D.vy[pop[q]] == T(0) ? st.out_field : F_P) + pop[q]);
     }
     const bool row1 = 2 * line + 1 < ny;
-    const PopXEpi<T, R, TPL, P> epi{D, pop, arena<T>(I), cf, basep, outp, has_base, line, t, nx, row1,
-                                    T(I.b), c, inv_tau};
+    EqT<T> fref[P];
+#pragma unroll
+    for (int q = 0; q < P; ++q) fref[q] = EqT<T>(I.fref[pop[q]]);
+    const PopXEpi<T, R, TPL, P> epi{D, eq_table(dvm, dvm64), pop, arena<T>(I), cf, basep, outp, has_base,
+                                    line, t, nx, row1, EqT<T>(I.b), c, ct, fref};
     using Epi = PopXEpi<T, R, TPL, P>;
     T ev[2][Epi::G][Epi::NV];
     // FP64, P > 1: the first group of epilogue inputs is requested before the transforms (its latency
     // then hides behind them; the registers are free at the occupancy FP64 blocks run at)
-    constexpr bool EARLY = sizeof(T) == 8 && P > 1 && LB_EPI_EARLY_F64;
+    constexpr bool EARLY = P > 1 && (sizeof(T) == 8 ? LB_EPI_EARLY_F64 : LB_EPI_EARLY_F32);
     if constexpr (EARLY) {
         if (active) epi.load(0, ev[0]);
     }
@@ -599,12 +693,12 @@ pop_x_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
 
 // Population y pass: one block = (instance, tile of column pairs, population i with v_y != 0).
 //   out = partial - c v_y D_y f
-template <typename T, int N>
-__global__ void __launch_bounds__((LineCfg<T, N, 1>::WG))
+template <typename T, int N, int MAXT = LB_YMAX_THREADS>
+__global__ void __launch_bounds__((LineCfg<T, N, 1, 0, MAXT>::WG))
 pop_y_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, int ngroups,
            int ntiles, const DvmConst<T>* __restrict__ dvm, const int* __restrict__ pops, int npops,
            StageArgs st) {
-    using C = LineCfg<T, N, 1>;
+    using C = LineCfg<T, N, 1, 0, MAXT>;
     constexpr int R = C::R, TPL = C::TPL, LPW = C::LPW;
     __shared__ cpx<T> lds_all[C::LDS];
     const BlockWork w = LB_JOBMAJOR_Y ? decode_block_jm(blockIdx.x, ngroups, ntiles, npops)
@@ -669,6 +763,8 @@ moments_kernel(const InstDesc* __restrict__ insts, const int* __restrict__ ilist
                const DvmConst<T>* __restrict__ dvm, int f_field) {
     LB_POINTWISE_PROLOGUE
     const DvmConst<T>& D = *dvm;
+    // the stored state is f - fref: its moments plus those of the reference (whose momentum
+    // vanishes: the reference is at rest)
     T r = 0, jx = 0, jy = 0, en = 0;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
@@ -678,6 +774,8 @@ moments_kernel(const InstDesc* __restrict__ insts, const int* __restrict__ ilist
         jy += f * D.vy[i];
         en += f * D.w[i];
     }
+    r = T(I.rho_ref) + r;
+    en = T(I.e_ref) + en;
     const T ux = jx / r, uy = jy / r;
     fieldp<T>(I, RHO)[e] = r;
     fieldp<T>(I, UX)[e] = ux;
@@ -744,7 +842,7 @@ finalize_kernel(const InstDesc* __restrict__ insts, const int* __restrict__ ilis
 }
 
 // Initial populations f = f^eq(rho0, u0, T0), computed in float64 from float64 inputs staged in
-// the F_B block (4 double fields), stored in the working precision into F_A.
+// the F_B block (4 double fields), stored as f - fref in the working precision into F_A.
 template <typename T>
 __global__ void __launch_bounds__(256)
 init_kernel(const InstDesc* __restrict__ insts, const int* __restrict__ ilist,
@@ -757,7 +855,7 @@ init_kernel(const InstDesc* __restrict__ insts, const int* __restrict__ ilist,
 #pragma unroll
     for (int i = 0; i < 16; ++i) f[i] = feq_pop<double>(*dvm, i, rho, ux, uy, Tm, I.b);
 #pragma unroll
-    for (int i = 0; i < 16; ++i) fieldp<T>(I, F_A + i)[e] = T(f[i]);
+    for (int i = 0; i < 16; ++i) fieldp<T>(I, F_A + i)[e] = T(f[i] - I.fref[i]);
 }
 
 // Per-cell conserved densities, summed per block in float64 (grid: red_blocks x instances):

@@ -18,6 +18,9 @@ struct LaunchSet {
     // when set, the launch timestamps its own start and end into these events
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;
     int ppb = 1;   // populations per block of the x population pass (tuned per size class)
+    // population y pass: the wide tile variant (blocks of up to LB_YMAX_THREADS_WIDE threads),
+    // tuned per size class, used where it exists
+    int ywide = 0;
 };
 
 // Launch through hipExtLaunchKernelGGL when the set carries timing events.
@@ -30,15 +33,30 @@ struct LaunchSet {
             hipLaunchKernelGGL(kernel, grid, block, 0, (L).stream, __VA_ARGS__);                \
     } while (0)
 
+// Set the calling thread's error message (lb_last_error) and return `status`.
+int set_error(int status, const char* msg);
+
 // Line passes (lb_lines_<dir>_<prec>.hip).
 hipError_t macro_x_f64(const LaunchSet& L, const JobDesc* jobs, int njobs);
 hipError_t macro_y_f64(const LaunchSet& L, const JobDesc* jobs, int njobs);
 hipError_t macro_x_f32(const LaunchSet& L, const JobDesc* jobs, int njobs);
 hipError_t macro_y_f32(const LaunchSet& L, const JobDesc* jobs, int njobs);
-hipError_t pop_x_f64(const LaunchSet& L, const DvmConst<double>* dvm, const int* pops, int npops, StageArgs st);
-hipError_t pop_y_f64(const LaunchSet& L, const DvmConst<double>* dvm, const int* pops, int npops, StageArgs st);
-hipError_t pop_x_f32(const LaunchSet& L, const DvmConst<float>* dvm, const int* pops, int npops, StageArgs st);
-hipError_t pop_y_f32(const LaunchSet& L, const DvmConst<float>* dvm, const int* pops, int npops, StageArgs st);
+// Population passes: dvm64 is the float64 velocity set the x pass forms the equilibrium with
+// (unused by the y pass); pops/npops list the y populations (y pass), or npops is the populations
+// per block of the x pass.
+hipError_t pop_x_f64(const LaunchSet& L, const DvmConst<double>* dvm, const DvmConst<double>* dvm64,
+                     const int* pops, int npops, StageArgs st);
+hipError_t pop_y_f64(const LaunchSet& L, const DvmConst<double>* dvm, const DvmConst<double>* dvm64,
+                     const int* pops, int npops, StageArgs st);
+hipError_t pop_x_f32(const LaunchSet& L, const DvmConst<float>* dvm, const DvmConst<double>* dvm64,
+                     const int* pops, int npops, StageArgs st);
+hipError_t pop_y_f32(const LaunchSet& L, const DvmConst<float>* dvm, const DvmConst<double>* dvm64,
+                     const int* pops, int npops, StageArgs st);
+
+// Whether the population y pass of y lines of n points has the wide-tile variant
+// (lb_lines_y_<prec>.hip).
+bool wide_y_f64(int n);
+bool wide_y_f32(int n);
 
 // Fused x + y macroscopic passes of square grids (lb_lines_xy_<prec>.hip).
 hipError_t macro_xy_f64(const LaunchSet& L, const JobDesc* jx, int njx, const JobDesc* jy, int njy);

@@ -47,16 +47,6 @@ lb_status fail(lb_status s, const char* fmt, ...) {
 constexpr size_t ALIGN = 256;
 inline size_t align_up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
 
-bool line_ok(int n) {
-    static const int sizes[] = {8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768,
-                                1024, 1536, 2048};
-    for (int s : sizes)
-        if (s == n) return true;
-    return false;
-}
-
-bool grid_ok(int nx, int ny) { return line_ok(nx) && (line_ok(ny) || ny == 1 || ny == 2); }
-
 // The kernels address an instance's field arena through one buffer descriptor with 32-bit byte
 // offsets, so the largest arena (2048 x 2048 cells in FP64) must stay below 2^32 bytes.
 static_assert((unsigned long long)NFIELDS * 2048 * 2048 * 8 < (1ull << 32),
@@ -156,6 +146,12 @@ bool build_dvm(const lb_dvm& d, DvmConst<double>& D) {
 
 }  // namespace
 
+// The thread's error message, set by the other host unit of the library.
+int lbfft::set_error(int status, const char* msg) {
+    g_err = msg;
+    return status;
+}
+
 struct lb_ctx {
     int n = 0;
     lb_precision prec = LB_FP64;
@@ -180,6 +176,7 @@ struct lb_ctx {
     struct Class {
         int nx, ny, start, count;
         int ppb = 1;   // tuned populations per block of the x population pass
+        int ywide = 0;   // tuned y tile of the population y pass (wide variant where it exists)
         bool hist = false;   // some instance keeps a per-step conservation history
     };
     std::vector<Class> classes;
@@ -191,6 +188,7 @@ struct lb_ctx {
     int graph_steps = LB_GRAPH_STEPS;
     bool use_graph = true;
     int ppb_override = 0;   // populations per x-pass block forced by LBFFT_PPB (1, 2 or 4), else tuned
+    int ywide_override = -1;  // y tile variant forced by LBFFT_YWIDE (0 or 1), else tuned
     bool fuse_xy = true;    // square grids: x and y macroscopic passes in one launch (LBFFT_FUSE_XY=0: off)
 
     template <typename Q>
@@ -255,9 +253,14 @@ void build_jobs(lb_ctx& c) {
     c.j_dyy = c.j_dxx;
 }
 
+void apply_plan(const lb_ctx& c, const lb_ctx::Class& k, LaunchSet& L) {
+    L.ppb = c.ppb_override ? c.ppb_override : k.ppb;
+    L.ywide = c.ywide_override >= 0 ? c.ywide_override : k.ywide;
+}
+
 LaunchSet set_of(const lb_ctx& c, const lb_ctx::Class& k) {
     LaunchSet L{c.d_insts(), c.d_ilist(k.start), k.count, k.nx, k.ny, c.stream};
-    L.ppb = k.ppb;
+    apply_plan(c, k, L);
     return L;
 }
 
@@ -265,8 +268,13 @@ LaunchSet set_one(const lb_ctx& c, int inst, hipStream_t s) {
     // the second half of ilist is the identity map
     LaunchSet L{c.d_insts(), c.d_ilist(c.n + inst), 1, c.p[inst].nx, c.p[inst].ny, s};
     for (const auto& k : c.classes)
-        if (k.nx == L.nx && k.ny == L.ny) L.ppb = k.ppb;
+        if (k.nx == L.nx && k.ny == L.ny) apply_plan(c, k, L);
     return L;
+}
+
+// Whether the class's population y pass has the wide-tile variant to tune.
+bool class_has_wide(const lb_ctx& c, const lb_ctx::Class& k) {
+    return c.prec == LB_FP64 ? wide_y_f64(k.ny) : wide_y_f32(k.ny);
 }
 
 // The x and y macroscopic passes of a square grid run as one fused launch, issued in the x slot.
@@ -304,15 +312,17 @@ struct PassHook {
 
 hipError_t pop_x(const lb_ctx& c, const LaunchSet& L, StageArgs st) {
     const int* pops = c.dev<int>(c.lay.pops);
-    const int ppb = c.ppb_override ? c.ppb_override : L.ppb;
-    if (c.prec == LB_FP64) return pop_x_f64(L, c.dev<DvmConst<double>>(c.lay.dvm64), pops, ppb, st);
-    return pop_x_f32(L, c.dev<DvmConst<float>>(c.lay.dvm32), pops, ppb, st);
+    const int ppb = L.ppb;
+    const DvmConst<double>* d64 = c.dev<DvmConst<double>>(c.lay.dvm64);
+    if (c.prec == LB_FP64) return pop_x_f64(L, d64, d64, pops, ppb, st);
+    return pop_x_f32(L, c.dev<DvmConst<float>>(c.lay.dvm32), d64, pops, ppb, st);
 }
 
 hipError_t pop_y(const lb_ctx& c, const LaunchSet& L, StageArgs st) {
     const int* pops = c.dev<int>(c.lay.pops);
-    if (c.prec == LB_FP64) return pop_y_f64(L, c.dev<DvmConst<double>>(c.lay.dvm64), pops, c.npops, st);
-    return pop_y_f32(L, c.dev<DvmConst<float>>(c.lay.dvm32), pops, c.npops, st);
+    const DvmConst<double>* d64 = c.dev<DvmConst<double>>(c.lay.dvm64);
+    if (c.prec == LB_FP64) return pop_y_f64(L, d64, d64, pops, c.npops, st);
+    return pop_y_f32(L, c.dev<DvmConst<float>>(c.lay.dvm32), d64, pops, c.npops, st);
 }
 
 // Launch pass `kind` of one stage for the instances of L.
@@ -457,50 +467,101 @@ hipError_t build_graph(const lb_ctx& c, int nsteps, hipGraph_t* graph, hipGraphE
     return e;
 }
 
-// Populations per block of the x population pass: time 1, 2 and 4 on the class's own data
-// (stage-1 arguments, which leave the state untouched) and keep the fastest.
-hipError_t tune_class(lb_ctx& c, lb_ctx::Class& cl) {
-    LaunchSet L = set_of(c, cl);
-    hipError_t e = force_passes(c, L, F_A);
-    if (e != hipSuccess) return e;
-    const StageArgs st{F_A, F_A, F_B, 0.5, 1};
+// Best-of-rounds timing of launch candidates on the stream: every round launches each candidate
+// once (interleaved, so clock and cache drift touch all of them); the first round only warms up.
+// Returns the index of the fastest candidate in *best.
+template <typename Launch>
+hipError_t time_candidates(const lb_ctx& c, int ncand, Launch launch, float* best_ms, int* best) {
     hipEvent_t a, b;
-    if ((e = hipEventCreate(&a)) != hipSuccess) return e;
-    if ((e = hipEventCreate(&b)) != hipSuccess) return e;
-    // each candidate's best of 6 launches, the candidates interleaved so that clock and cache
-    // drift between rounds touches all of them (the first round only warms up)
-    const int cand[3] = {1, 2, 4};
-    float best_ms[3] = {1e30f, 1e30f, 1e30f};
+    hipError_t e = hipEventCreate(&a);
+    if (e != hipSuccess) return e;
+    if ((e = hipEventCreate(&b)) != hipSuccess) {
+        (void)hipEventDestroy(a);
+        return e;
+    }
+    for (int k = 0; k < ncand; ++k) best_ms[k] = 1e30f;
     for (int round = 0; round < 7 && e == hipSuccess; ++round)
-        for (int k = 0; k < 3 && e == hipSuccess; ++k) {
-            L.ppb = cand[k];
+        for (int k = 0; k < ncand && e == hipSuccess; ++k) {
             e = hipEventRecord(a, c.stream);
-            if (e == hipSuccess) e = pop_x(c, L, st);
+            if (e == hipSuccess) e = launch(k);
             if (e == hipSuccess) e = hipEventRecord(b, c.stream);
             if (e == hipSuccess) e = hipEventSynchronize(b);
             float t = 0.f;
             if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
             if (e == hipSuccess && round > 0 && t < best_ms[k]) best_ms[k] = t;
         }
-    if (e == hipSuccess) {
-        int kb = 0;
-        for (int k = 0; k < 3; ++k) {
-            if (std::getenv("LBFFT_VERBOSE"))
-                std::fprintf(stderr, "lbfft tune: class %dx%d x%d  pops/block %d  %.4f ms\n", cl.nx,
-                             cl.ny, cl.count, cand[k], best_ms[k]);
-            if (best_ms[k] < best_ms[kb]) kb = k;
-        }
-        cl.ppb = cand[kb];
-    }
+    *best = 0;
+    for (int k = 1; k < ncand; ++k)
+        if (best_ms[k] < best_ms[*best]) *best = k;
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
     return e;
+}
+
+// Launch plan of one size class, measured on the class's own data with stage-1 arguments (which
+// leave the state untouched): populations per block of the x population pass (1, 2, 4), then --
+// where the class's population y pass has the wide variant -- its y tile.  Fixed choices
+// (LBFFT_PPB, LBFFT_YWIDE) are not re-tuned.
+hipError_t tune_class(lb_ctx& c, lb_ctx::Class& cl) {
+    const bool verbose = std::getenv("LBFFT_VERBOSE") != nullptr;
+    LaunchSet L = set_of(c, cl);
+    hipError_t e = force_passes(c, L, F_A);
+    if (e != hipSuccess) return e;
+    const StageArgs st{F_A, F_A, F_B, 0.5, 1};
+    float ms[3];
+    int best = 0;
+    if (!c.ppb_override) {
+        const int cand[3] = {1, 2, 4};
+        e = time_candidates(c, 3, [&](int k) { L.ppb = cand[k]; return pop_x(c, L, st); }, ms, &best);
+        if (e != hipSuccess) return e;
+        cl.ppb = cand[best];
+        if (verbose)
+            for (int k = 0; k < 3; ++k)
+                std::fprintf(stderr, "lbfft tune: class %dx%d x%d  pops/block %d  %.4f ms\n", cl.nx,
+                             cl.ny, cl.count, cand[k], ms[k]);
+    }
+    L = set_of(c, cl);
+    if ((e = pop_x(c, L, st)) != hipSuccess) return e;   // the partial sums the y pass adds to
+    if (c.ywide_override < 0 && class_has_wide(c, cl)) {
+        e = time_candidates(c, 2, [&](int k) { L.ywide = k; return pop_y(c, L, st); }, ms, &best);
+        if (e != hipSuccess) return e;
+        cl.ywide = best;
+        if (verbose)
+            std::fprintf(stderr, "lbfft tune: class %dx%d  pop y tile default %.4f wide %.4f ms\n",
+                         cl.nx, cl.ny, ms[0], ms[1]);
+    }
+    return hipSuccess;
 }
 
 lb_status check_inst(const lb_ctx* c, int inst) {
     if (!c) return fail(LB_E_ARG, "null context");
     if (inst < 0 || inst >= c->n) return fail(LB_E_ARG, "instance %d out of range [0,%d)", inst, c->n);
     return LB_OK;
+}
+
+// Reference populations of an FP32 instance (the arena stores f - fref): the equilibrium at rest of
+// the mean initial temperature and of the mean initial density rounded to float32 (so that the
+// moment kernel adds an exact rho_ref), in float64 (Sec. 2.1, seven kinetic moments at u = 0).
+void set_reference(const DvmConst<double>& D, const lb_params& q, const double* rho0, const double* T0,
+                   InstDesc& I) {
+    const int64_t nc = (int64_t)q.nx * q.ny;
+    double sr = 0.0, st = 0.0;
+    for (int64_t e = 0; e < nc; ++e) {
+        sr += rho0[e];
+        st += T0[e];
+    }
+    const double rho = (double)(float)(sr / nc), T = st / nc, b = q.b_dof;
+    // Maxwellian moments per unit density at u = 0 in the row order of the moment matrix
+    const double h2 = (b + 2.0) * T;
+    const double m[16] = {1, 0, 0, b * T, T, 0, T, 0, 0, 0, 0, 0, 0, h2 * T, 0, h2 * T};
+    I.rho_ref = rho;
+    I.e_ref = 0.0;
+    for (int i = 0; i < 16; ++i) {
+        double s = 0.0;
+        for (int j = 0; j < 16; ++j) s += D.cinv[i][j] * m[j];
+        I.fref[i] = rho * s;
+        I.e_ref += I.fref[i] * D.w[i];
+    }
 }
 
 // Copy field `fid` of instance inst (nc words of the working precision) to host float64.
@@ -641,6 +702,9 @@ lb_status lb_init(lb_ctx** out, int n_inst, const lb_params* p, const lb_dvm* dv
         const int v = std::atoi(g);
         if (v == 1 || v == 2 || v == 4) c->ppb_override = v;
     }
+    if (const char* g = std::getenv("LBFFT_YWIDE")) {
+        if (g[0] == '0' || g[0] == '1') c->ywide_override = g[0] - '0';
+    }
 
     if (!build_dvm(c->dvm, c->dvm64)) {
         delete c;
@@ -721,6 +785,8 @@ lb_status lb_init(lb_ctx** out, int n_inst, const lb_params* p, const lb_dvm* dv
         I.hist_len = p[k].hist_len;
         I.dx = p[k].dx; I.dt = p[k].dt; I.tau = p[k].tau; I.K = p[k].K; I.H = p[k].H;
         I.zeta = p[k].zeta; I.q = p[k].q; I.b = p[k].b_dof; I.a = p[k].vdw_a; I.bw = p[k].vdw_b;
+        // FP64 stores f itself (fref = 0); FP32 stores the deviation from a reference equilibrium
+        if (prec == LB_FP32) set_reference(c->dvm64, p[k], rho0[k], T0[k], I);
     }
     std::vector<int> order;
     for (int k = 0; k < n_inst; ++k) {
@@ -799,7 +865,7 @@ lb_status lb_init(lb_ctx** out, int n_inst, const lb_params* p, const lb_dvm* dv
         if (!ok) break;
         const int64_t cells = (int64_t)cl.nx * cl.ny * cl.count;
         cl.ppb = cells >= (1 << 20) ? 2 : 1;   // default without tuning
-        if (tune && !c->ppb_override) {
+        if (tune && (!c->ppb_override || c->ywide_override < 0)) {
             hipError_t e = tune_class(*c, cl);
             if (e != hipSuccess) {
                 ok = false;
@@ -961,14 +1027,25 @@ lb_status lb_get_f(lb_ctx* c, int inst, double* f) {
     lb_status s = check_inst(c, inst);
     if (s != LB_OK) return s;
     if (!f) return fail(LB_E_ARG, "f is NULL");
-    return field_to_host(c, inst, F_A, f, 16);
+    if ((s = field_to_host(c, inst, F_A, f, 16)) != LB_OK) return s;
+    // the arena holds f - fref (fref = 0 in FP64)
+    const InstDesc& I = c->hinst[inst];
+    if (c->prec == LB_FP32)
+        for (int i = 0; i < 16; ++i)
+            for (int64_t e = 0; e < I.ncell; ++e) f[i * I.ncell + e] += I.fref[i];
+    return LB_OK;
 }
 
 lb_status lb_set_f(lb_ctx* c, int inst, const double* f) {
     lb_status s = check_inst(c, inst);
     if (s != LB_OK) return s;
     if (!f) return fail(LB_E_ARG, "f is NULL");
-    return field_from_host(c, inst, F_A, f, 16);
+    const InstDesc& I = c->hinst[inst];
+    if (c->prec == LB_FP64) return field_from_host(c, inst, F_A, f, 16);
+    std::vector<double> g((size_t)16 * I.ncell);
+    for (int i = 0; i < 16; ++i)
+        for (int64_t e = 0; e < I.ncell; ++e) g[i * I.ncell + e] = f[i * I.ncell + e] - I.fref[i];
+    return field_from_host(c, inst, F_A, g.data(), 16);
 }
 
 lb_status lb_set_moments(lb_ctx* c, int inst, const double* rho, const double* ux, const double* uy,
@@ -1016,9 +1093,10 @@ lb_status lb_plan_info(lb_ctx* c, int inst, int* out, int n) {
     lb_status s = check_inst(c, inst);
     if (s != LB_OK) return s;
     if (!out || n < 2) return fail(LB_E_ARG, "need an output array of length >= 2");
-    out[0] = set_one(*c, inst, c->stream).ppb;
-    if (c->ppb_override) out[0] = c->ppb_override;
-    out[1] = (int)c->classes.size();
+    const LaunchSet L = set_one(*c, inst, c->stream);
+    const int wide = c->prec == LB_FP64 ? wide_y_f64(L.ny) : wide_y_f32(L.ny);
+    const int v[3] = {L.ppb, (int)c->classes.size(), wide && L.ywide ? 1 : 0};
+    for (int k = 0; k < n && k < 3; ++k) out[k] = v[k];
     return LB_OK;
 }
 

@@ -52,7 +52,23 @@ struct InstDesc {
     int32_t red_blocks;    // blocks of the partial-sum kernel
     int32_t hist_len;      // ring-buffer length (0: no per-step history)
     double dx, dt, tau, K, H, zeta, q, b, a, bw;
+    // Reference populations of the stored state: the arena holds f - fref (FP32 contexts: fref =
+    // f^eq(rho_ref, 0, T_ref) of the instance's mean initial density and temperature, so that the
+    // stored deviations are small and their rounding too; FP64 contexts: fref = 0, the plain f).
+    // rho_ref and e_ref are the density and energy moments sum fref and sum fref (v^2 + eta^2);
+    // rho_ref is exactly representable in float32.
+    double fref[16];
+    double rho_ref, e_ref;
 };
+
+// Line lengths of the transforms: 2^a and 3 * 2^a from 8 to 2048.  A grid takes them along x,
+// and along y also 1 or 2 (quasi-1-D: the y-derivative vanishes).
+inline constexpr bool line_ok(int n) {
+    for (int p = 8; p <= 2048; p *= 2)
+        if (n == p || (n == 3 * p / 2 && n <= 1536)) return true;
+    return false;
+}
+inline constexpr bool grid_ok(int nx, int ny) { return line_ok(nx) && (line_ok(ny) || ny == 1 || ny == 2); }
 
 // Conservation partial-sum blocks per instance (each block strides over the grid).
 constexpr int RED_BLOCKS = 512;

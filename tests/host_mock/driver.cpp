@@ -32,6 +32,15 @@ int main() {
     st = lb_init(&c, 3, q, nullptr, LB_FP32, rr, xx, xx, tt, mem, ws, nullptr);
     printf("init2 %d %s\n", st, lb_last_error());
     lb_step(c, 2); lb_free(c); free(mem);
+    // long columns: a class whose population y pass has a wide variant to tune
+    lb_params w = p; w.nx = 24; w.ny = 1024;
+    std::vector<double> r3(24 * 1024, 3.5), z3(24 * 1024, 0), t3(24 * 1024, 0.514);
+    const double* r3p[1] = {r3.data()}; const double* z3p[1] = {z3.data()}; const double* t3p[1] = {t3.data()};
+    ws = lb_workspace_bytes(1, &w, LB_FP32); mem = aligned_alloc(256, ws);
+    st = lb_init(&c, 1, &w, nullptr, LB_FP32, r3p, z3p, z3p, t3p, mem, ws, nullptr);
+    int plan[3] = {0, 0, -1};
+    printf("init3 %d %d\n", st, lb_plan_info(c, 0, plan, 3));
+    lb_step(c, 1); lb_free(c); free(mem);
     printf("done\n");
     return 0;
 }

@@ -8,8 +8,10 @@ static void chk(const LaunchSet& L) { assert(L.insts && L.ilist && L.ninst > 0 &
 M(macro_x_f64, double) M(macro_y_f64, double) M(macro_x_f32, float) M(macro_y_f32, float)
 #define MXY(name) hipError_t name(const LaunchSet& L, const JobDesc* a, int na, const JobDesc* b, int nb) { chk(L); assert(L.nx == L.ny && a && b && na > 0 && nb > 0); return hipSuccess; }
 MXY(macro_xy_f64) MXY(macro_xy_f32)
-#define P(name, T) hipError_t name(const LaunchSet& L, const DvmConst<T>* d, const int* p, int n, StageArgs) { chk(L); assert(d && p); return hipSuccess; }
+#define P(name, T) hipError_t name(const LaunchSet& L, const DvmConst<T>* d, const DvmConst<double>* d64, const int* p, int n, StageArgs) { chk(L); assert(d && d64 && p && n > 0); return hipSuccess; }
 P(pop_x_f64, double) P(pop_y_f64, double) P(pop_x_f32, float) P(pop_y_f32, float)
+bool wide_y_f64(int) { return false; }
+bool wide_y_f32(int n) { return n >= 1024; }
 template <typename T> hipError_t launch_moments(const LaunchSet& L, const DvmConst<T>*, int) { chk(L); return hipSuccess; }
 template <typename T> hipError_t launch_stress(const LaunchSet& L) { chk(L); return hipSuccess; }
 template <typename T> hipError_t launch_finalize(const LaunchSet& L) { chk(L); return hipSuccess; }

@@ -1,10 +1,11 @@
 """GPU parity at the benchmark sizes, in the launch configuration the benchmark times.
 
-Where the oracle is too slow to run inside a test (512^2 for 100 steps, the ragged batch with
-grids up to 1024^2 for 50 steps, 2048^2 for 5 steps), the HIP results are compared with oracle
-samples written by tests/golden/make_oracle_samples.py (oracle only: moments at a fixed random
-sample of cells plus each field's max |value| over the grid, the denominators of the parity
-norm)."""
+The 512^2 FP64 headline workload is compared over the full field after every one of its first 100
+steps, and one instance of every size class of the ragged batch over the full field at step 50,
+with the oracle run live on the host.  Every instance of the ragged batch, the 512^2 FP32 run and
+the 2048^2 run are also compared with oracle samples written by tests/golden/make_oracle_samples.py
+(oracle only: moments at a fixed random sample of cells plus each field's max |value| over the
+grid, the denominators of the parity norm)."""
 import os
 
 import numpy as np
@@ -12,7 +13,9 @@ import pytest
 
 from oracle import model, spectral
 from paper_1403_3746_amd import workloads as W
+from tests import oracle_pool
 from tests.gpu_util import field_errors, say
+from tests.oracle_pool import oracle_workers
 
 pytestmark = pytest.mark.gpu
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
@@ -53,17 +56,24 @@ def _sample_errors(mom_gpu, z, key, step):
     return e
 
 
-def test_quench512_fp64_first_steps_live(torch_cuda):
+@pytest.mark.timeout(900)
+def test_quench512_fp64_every_step_100_live(torch_cuda):
+    # the benchmark's headline workload: the full field after each of the first 100 steps against
+    # the oracle stepped alongside on the host
     (p, ic), = W.config("quench512")[0]
-    spectral.set_workers(os.cpu_count() or 1)
+    spectral.set_workers(oracle_workers())
     sim = _sim([(p, ic)], "fp64")
     f_ref = model.init_equilibrium(*ic, p)
-    for n in range(1, 4):
+    worst = 0.0
+    for n in range(1, 101):
         sim.step(1)
         f_ref = model.rk2_step(f_ref, p)
         errs = field_errors(sim.get_f(), f_ref, lambda f: model.moments(f, p))
-        say(f"quench512 fp64 step {n}: {errs}")
-        assert max(errs.values()) < 1e-12
+        worst = max(worst, max(errs.values()))
+        if n in (1, 2, 3, 10, 50, 100):
+            say(f"quench512 fp64 step {n}: {errs}")
+        assert max(errs.values()) < 1e-12, (n, errs)
+    say(f"quench512 fp64 worst over 100 steps: {worst:.2e}")
     spectral.set_workers(1)
     sim.close()
 
@@ -106,6 +116,30 @@ def test_batch128x256_fp32_step50(torch_cuda, monkeypatch):
     sim.close()
 
 
+@pytest.mark.timeout(900)
+def test_ragged64_fp32_full_field_step50_per_size_class(torch_cuda):
+    # one instance of every size class of the ragged batch (64^2 ... 1024^2), full field at step 50
+    # against the oracle run live in worker processes, the batch run as the benchmark runs it
+    insts, _ = W.config("ragged64")
+    first = {}
+    for k, (_, ic) in enumerate(insts):
+        first.setdefault(ic[0].shape, k)
+    ks = sorted(first.values())
+    ref = oracle_pool.moments_at("ragged64", ks, 50)
+    sim = _sim(insts, "fp32")
+    sim.step(50)
+    for k in ks:
+        r0, ux0, uy0, T0 = ref[k]
+        r1, ux1, uy1, T1 = sim.moments(k)
+        s = np.sqrt(np.abs(T0).max())
+        e = dict(rho=float(np.abs(r1 - r0).max() / np.abs(r0).max()),
+                 T=float(np.abs(T1 - T0).max() / np.abs(T0).max()),
+                 u=float(max(np.abs(ux1 - ux0).max(), np.abs(uy1 - uy0).max()) / s))
+        say(f"ragged64 inst {k} {insts[k][1][0].shape} fp32 step 50 full field: {e}")
+        assert e["rho"] < 1e-5 and e["T"] < 1e-5, (k, e)
+    sim.close()
+
+
 def test_ragged64_fp32_every_instance_step50(torch_cuda):
     z = _samples("ragged64")
     insts, _ = W.config("ragged64")
@@ -135,7 +169,7 @@ def test_quench2048_fp32_step5_vs_oracle_samples(torch_cuda):
 
 def test_quench2048_fp32_conservation(torch_cuda):
     (p, ic), = W.config("quench2048")[0]
-    spectral.set_workers(os.cpu_count() or 1)
+    spectral.set_workers(oracle_workers())
     ref = model.conservation(model.init_equilibrium(*ic, p), p)
     spectral.set_workers(1)
     sim = _sim([(dict(p, hist=200), ic)], "fp32")
@@ -149,17 +183,18 @@ def test_quench2048_fp32_conservation(torch_cuda):
     assert np.array_equal(h[0], c0)
     drift = (h[-1] - h[0]) / abs(h[0, 0])
     say(f"quench2048 fp32 drift after 100 steps (relative to mass): {drift}")
-    assert abs(drift[0]) < 1e-6 and abs(drift[1]) < 1e-6 and abs(drift[2]) < 1e-6
+    assert abs(drift[0]) < 1e-9 and abs(drift[1]) < 1e-9 and abs(drift[2]) < 1e-9
     sim.close()
 
 
-@pytest.mark.parametrize("name,prec", [("quench512", "fp64"), ("quench512", "fp32"), ("quench2048", "fp32")])
-def test_full_length_runs_conserve(torch_cuda, name, prec):
+@pytest.mark.parametrize("name,prec,tol", [("quench512", "fp64", 1e-12), ("quench512", "fp32", 1e-6),
+                                           ("quench2048", "fp32", 3e-7)])
+def test_full_length_runs_conserve(torch_cuda, name, prec, tol):
     # the whole run of each single-domain workload (10 000 steps at 512^2, 5 000 at 2048^2):
     # finite throughout, with the FP64 grid integrals of mass and momentum drifting by at most
-    # rounding -- in FP64 ~1e-17 per step; in FP32 a systematic ~1.5e-9 per step from rounding in
-    # the step, hence 5e-5 over the run; the total energy is reported (the scheme conserves it
-    # only up to truncation)
+    # rounding.  In FP32 the state is stored as its deviation from a reference equilibrium and the
+    # equilibrium is formed in float64, so the rounding does not accumulate into a systematic drift
+    # (measured ~1e-10 over either run; before, 1.6e-5 and 2.7e-6).  The total energy is reported.
     insts, steps = W.config(name)
     sim = _sim(insts, prec)
     c0 = sim.conservation()
@@ -168,6 +203,5 @@ def test_full_length_runs_conserve(torch_cuda, name, prec):
     m0 = abs(c0[0])
     drift = (c1 - c0) / m0
     say(f"{name} {prec} after {steps} steps: drift (mass, momentum x, y, e_T) / mass = {drift}")
-    tol = 1e-12 if prec == "fp64" else 5e-5
     assert abs(drift[0]) < tol and abs(drift[1]) < tol and abs(drift[2]) < tol
     sim.close()

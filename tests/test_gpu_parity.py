@@ -121,9 +121,11 @@ def test_step_fp64_slab64_every_step(torch_cuda):
     sim.close()
 
 
-def test_step_fp64_nonsquare_with_all_terms(torch_cuda):
+@pytest.mark.parametrize("b", [2.0, 3.0])
+def test_step_fp64_nonsquare_with_all_terms(torch_cuda, b):
+    # 20 steps with every term of B, C, C_q switched on, b = 2 and b = 3 degrees of freedom
     ny, nx = 96, 64
-    p = W.base_params(q=-0.004, zeta=0.01, H=0.003, dx=0.5)
+    p = W.base_params(q=-0.004, zeta=0.01, H=0.003, dx=0.5, b=b)
     ic = W.smooth_random(nx, ny, 11, T0=0.5)
     sim = _sim([(p, ic)])
     f_ref = model.init_equilibrium(*ic, p)
@@ -132,7 +134,7 @@ def test_step_fp64_nonsquare_with_all_terms(torch_cuda):
         f_ref = model.rk2_step(f_ref, p)
         errs = field_errors(sim.get_f(), f_ref, _moments(p))
         assert max(errs.values()) < 1e-12, (n, errs)
-    say(f"nonsquare fp64 step 20: {errs}")
+    say(f"nonsquare fp64 b={b} step 20: {errs}")
     sim.close()
 
 
@@ -292,21 +294,25 @@ def test_full_step_square_sizes_of_three_times_pow2(torch_cuda, monkeypatch, ppb
         sim.close()
 
 
-@pytest.mark.parametrize("prec", ["fp64", "fp32"])
-def test_step_long_columns(torch_cuda, prec):
+@pytest.mark.parametrize("prec,ywide", [("fp64", "0"), ("fp32", "0"), ("fp32", "1")])
+def test_step_long_columns(torch_cuda, monkeypatch, prec, ywide):
     # tall grids: y lines of 768..2048 points (narrow column-pair tiles, blocks in job-major
-    # order), with the last tile partly empty where nx/2 is not a multiple of the tile width
+    # order), with the last tile partly empty where nx/2 is not a multiple of the tile width; in
+    # FP32 with the default and with the wide population y tiles
+    monkeypatch.setenv("LBFFT_YWIDE", ywide)
     tol = 1e-12 if prec == "fp64" else 2e-6
     for ny, nx in ((768, 24), (1024, 24), (1536, 12), (2048, 12)):
         p = W.base_params(q=-0.004, zeta=1e-3)
         ic = W.smooth_random(nx, ny, 7 + ny, T0=0.52)
         sim = _sim([(p, ic)], prec)
+        if prec == "fp32" and ny >= 1024:
+            assert sim.plan(0)["pop_y_wide"] == int(ywide)
         f_ref = model.init_equilibrium(*ic, p)
         for _ in range(3):
             f_ref = model.rk2_step(f_ref, p)
         sim.step(3)
         errs = field_errors(sim.get_f(), f_ref, _moments(p))
-        say(f"long columns {nx}x{ny} {prec} step 3: {errs}")
+        say(f"long columns {nx}x{ny} {prec} wide {ywide} step 3: {errs}")
         assert max(errs.values()) < tol, (ny, nx, errs)
         sim.close()
 

@@ -28,5 +28,5 @@ def test_host_runtime_under_sanitizers(tmp_path):
     r = subprocess.run([str(exe)], capture_output=True, text=True, timeout=300)
     assert r.returncode == 0, (r.stdout + r.stderr)[-4000:]
     lines = r.stdout.split("\n")
-    assert "init 0 " in lines and "init2 0 " in lines and "done" in lines, r.stdout
+    assert "init 0 " in lines and "init2 0 " in lines and "init3 0 0" in lines and "done" in lines, r.stdout
     assert "setmom 0" in lines and "setmom_bad -1" in lines, r.stdout
