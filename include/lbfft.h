@@ -157,6 +157,20 @@ lb_status lb_rhs(lb_ctx* ctx, int inst, double* R);
  * line-FFT kernels through the instance's scratch fields; synchronises. */
 lb_status lb_derivative(lb_ctx* ctx, int inst, int axis, int order, const double* g, double* out);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the windowed-FFT derivative of lb_derivative without a
+ * context or workspace.  d_g and d_out are float64 device arrays [ny][nx] (caller-owned; d_out may
+ * not alias d_g); the line pass runs in precision prec on the stream hip_stream of the current
+ * device.  Every buffer the kernels need (descriptor, tables, staging fields) lives in one static
+ * device array of the library that each GPU it runs on holds until the process ends; nothing is
+ * allocated.  Calls on one GPU share that array, so calls that overlap on one GPU (several streams
+ * or threads) race; it keeps the last call's contents, and each call writes everything it reads.
+ * Asynchronous.  Errors: LB_E_ARG (null pointer, dx <= 0, axis/order/prec invalid), LB_E_SIZE (grid
+ * not supported as in lb_params, or nx * ny > LB_NOALLOC_MAX_CELLS), LB_E_HIP. */
+#define LB_NOALLOC_MAX_CELLS (1 << 20)
+lb_status lb_derivative_noalloc(int nx, int ny, double dx, lb_precision prec, int axis, int order,
+                                const double* d_g, double* d_out, void* hip_stream);
+
 /* Pass kinds of one Runge-Kutta stage, in launch order (index into lb_step_timed's output).
  * The x and y passes of each macroscopic pair are independent and run concurrently in the
  * captured step. */

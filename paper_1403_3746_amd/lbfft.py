@@ -20,7 +20,7 @@ _STATUS = {0: "LB_OK", -1: "LB_E_ARG", -2: "LB_E_SIZE", -3: "LB_E_NOMEM", -4: "L
 
 EXPORTS = ("lb_workspace_bytes", "lb_init", "lb_step", "lb_sync", "lb_moments", "lb_conservation", "lb_conservation_history",
            "lb_get_f", "lb_set_f", "lb_set_moments", "lb_force_coefficients", "lb_rhs", "lb_derivative",
-           "lb_step_timed", "lb_plan_info", "lb_free", "lb_last_error")
+           "lb_step_timed", "lb_plan_info", "lb_free", "lb_last_error", "lb_derivative_noalloc")
 PASS_NAMES = ("moments", "macro_x1", "macro_y1", "stress", "macro_x2", "macro_y2", "finalize",
               "pop_x", "pop_y")
 
@@ -204,6 +204,18 @@ def lb_derivative(ctx, inst, axis, order, g):
     out = np.empty_like(g)
     _check(load().lb_derivative(ctx, inst, axis, order, _dptr(g), _dptr(out)))
     return out
+
+
+def lb_derivative_noalloc(nx, ny, dx, prec, axis, order, d_g, d_out, hip_stream):
+    """Windowed-FFT derivative of the float64 device field at address d_g ([ny][nx]) into d_out,
+    with no device allocation (the library's static scratch array)."""
+    lib = load()
+    fn = lib.lb_derivative_noalloc
+    fn.argtypes = [ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_int,
+                   ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]
+    fn.restype = ctypes.c_int
+    _check(fn(nx, ny, dx, prec, axis, order, ctypes.c_void_p(d_g), ctypes.c_void_p(d_out),
+              ctypes.c_void_p(hip_stream)))
 
 
 def lb_step_timed(ctx, n_steps):
