@@ -91,12 +91,14 @@ def load_traffic(workload, pass_name, pops_per_block=None):
     return None
 
 
-def run_gpu(instances, precision, steps, warmup, timed_steps):
+def run_gpu(instances, precision, steps, warmup, timed_steps, settle=None):
     import torch
     from paper_1403_3746_amd.lbfft import Sim
 
     sim = Sim(instances, precision)
     cells = sum(ic[0].size for _, ic in instances)
+    if settle is not None:
+        settle()      # GPU clocks up again after the context's set-up, before its warm-up steps
     sim.step(warmup)
     sim.sync()
     torch.cuda.synchronize()
@@ -117,25 +119,28 @@ def run_gpu(instances, precision, steps, warmup, timed_steps):
                 passes=passes, plan=plan)
 
 
-def gpu_warm(seconds):
-    """Untimed steps of a throwaway 512x512 FP64 context for about `seconds` of wall time before
-    anything is timed: a GPU that has just come out of idle runs its first tenths of a second a
-    few per cent slower than at its settled clocks."""
-    import torch
-    from paper_1403_3746_amd import workloads as W
-    from paper_1403_3746_amd.lbfft import Sim
+class GpuWarmer:
+    """A throwaway 512x512 FP64 context stepped untimed for a given wall time right before a timed
+    region: a GPU that has just come out of idle (or has sat through a context's set-up on the
+    host) runs its first tenths of a second a few per cent slower than at its settled clocks."""
 
-    insts, _ = W.config("quench512")
-    sim = Sim(insts, "fp64")
-    t0 = time.perf_counter()
-    steps = 0
-    while time.perf_counter() - t0 < seconds:
-        sim.step(64)
-        sim.sync()
-        steps += 64
-    torch.cuda.synchronize()
-    sim.close()
-    return round(time.perf_counter() - t0, 3)
+    def __init__(self):
+        from paper_1403_3746_amd import workloads as W
+        from paper_1403_3746_amd.lbfft import Sim
+
+        insts, _ = W.config("quench512")
+        self.sim = Sim(insts, "fp64")
+        self.total = 0.0
+
+    def spin(self, seconds):
+        t0 = time.perf_counter()
+        while time.perf_counter() - t0 < seconds:
+            self.sim.step(64)
+            self.sim.sync()
+        self.total += time.perf_counter() - t0
+
+    def close(self):
+        self.sim.close()
 
 
 def roofline(res, word_bytes, workload):
@@ -243,8 +248,8 @@ def main():
     ap.add_argument("--timed-steps", type=int, default=50)
     ap.add_argument("--no-variants", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--gpu-warm", type=float, default=1.0,
-                    help="seconds of untimed stepping of a throwaway context before any timing")
+    ap.add_argument("--gpu-warm", type=float, default=0.5,
+                    help="seconds of untimed stepping of a throwaway context before each timed run")
     ap.add_argument("--only", choices=("quench512_fp64", "quench512_fp32", "batch128x256_fp32",
                                        "ragged64_fp32", "quench2048_fp32", "slab64_fp64"),
                     help="run one workload only and print its summary (for profiling)")
@@ -270,15 +275,16 @@ def main():
         return
 
     insts, _ = W.config("quench512")
-    # settle the GPU's clocks first, and run the variants before the headline, so that a short
-    # timed region measures the steady rate of a long run
-    warm_s = gpu_warm(args.gpu_warm)
+    # every timed run starts on a GPU at its settled clocks (the variants also run before the
+    # headline), so that a short timed region measures the steady rate of a long run
+    warmer = GpuWarmer() if args.gpu_warm > 0 else None
+    settle = (lambda: warmer.spin(args.gpu_warm)) if warmer else None
     var, rb = {}, None
     if not args.no_variants:
 
         def variant(name, prec, steps, warmup, timed):
             vi, _ = W.config(name)
-            r = run_gpu(vi, prec, steps, warmup, timed)
+            r = run_gpu(vi, prec, steps, warmup, timed, settle)
             key = f"{name}_{prec}"
             return r, dict(mlups=round(r["mlups"], 2), ms_per_step=round(r["ms_per_step"], 5),
                            steps=steps, roofline=roofline(r, 8 if prec == "fp64" else 4, key),
@@ -292,7 +298,11 @@ def main():
         big_steps, big_warm = max(1, args.steps // 8), max(1, args.warmup // 4)
         _, var["quench2048_fp32"] = variant("quench2048", "fp32", big_steps, big_warm, 2)
         _, var["ragged64_fp32"] = variant("ragged64", "fp32", big_steps, big_warm, 2)
-    main_res = run_gpu(insts, "fp64", args.steps, args.warmup, args.timed_steps)
+    main_res = run_gpu(insts, "fp64", args.steps, args.warmup, args.timed_steps, settle)
+    warm_s = 0.0
+    if warmer:
+        warm_s = round(warmer.total, 3)
+        warmer.close()
     out = {
         "metric": METRIC,
         "value": round(main_res["mlups"], 2),

@@ -123,6 +123,54 @@ struct Dft<T, 8, INV> {
     }
 };
 
+// a * W16^m, W16 = exp(-+ 2 pi i / 16) (forward / inverse), for the internal twiddles of the
+// 16-point DFT (m = n2 k1 <= 9); m is a constant after unrolling, so the switch folds away and the
+// eighth and quarter turns cost no general product.
+template <typename T, bool INV>
+__device__ __forceinline__ cpx<T> w16(cpx<T> a, int m) {
+    const T c1 = T(0.92387953251128675613), s1 = T(0.38268343236508977173);
+    const T h = T(0.70710678118654752440);
+    // forward W16^m = (cos t, -sin t), t = pi m / 8; the inverse conjugates
+    auto mul = [](cpx<T> x, T c, T sn) -> cpx<T> {
+        const T si = INV ? -sn : sn;   // multiply by (c, -si)
+        return {x.re * c + x.im * si, x.im * c - x.re * si};
+    };
+    switch (m) {
+        case 0: return a;
+        case 1: return mul(a, c1, s1);
+        case 2: return INV ? cpx<T>{h * (a.re - a.im), h * (a.re + a.im)} : cpx<T>{h * (a.re + a.im), h * (a.im - a.re)};
+        case 3: return mul(a, s1, c1);
+        case 4: return rot90<T, INV>(a);
+        case 6: return INV ? cpx<T>{h * (-a.re - a.im), h * (a.re - a.im)} : cpx<T>{h * (a.im - a.re), h * (-a.re - a.im)};
+        case 9: return mul(a, -c1, -s1);
+        default: return mul(a, T(0), T(0));   // not reached: m = n2 k1 takes the values above
+    }
+}
+
+// 16-point DFT as 4 x 4: element n = 4 n1 + n2, output k = k1 + 4 k2; 4-point DFTs over n1, the
+// internal twiddles W16^(n2 k1), 4-point DFTs over n2.
+template <typename T, bool INV>
+struct Dft<T, 16, INV> {
+    __device__ __forceinline__ static void run(cpx<T>* v) {
+        cpx<T> b[4][4];
+#pragma unroll
+        for (int n2 = 0; n2 < 4; ++n2) {
+#pragma unroll
+            for (int n1 = 0; n1 < 4; ++n1) b[n2][n1] = v[4 * n1 + n2];
+            Dft<T, 4, INV>::run(b[n2]);
+#pragma unroll
+            for (int k1 = 1; k1 < 4; ++k1) b[n2][k1] = w16<T, INV>(b[n2][k1], n2 * k1);
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < 4; ++k1) {
+            cpx<T> c[4] = {b[0][k1], b[1][k1], b[2][k1], b[3][k1]};
+            Dft<T, 4, INV>::run(c);
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) v[k1 + 4 * k2] = c[k2];
+        }
+    }
+};
+
 // ---------------------------------------------------------------------------------------
 // Radix plans.  R (elements per thread) and the pass radices are compile-time functions of N.
 // Supported N: 1, 2 and 2^a, 3*2^a for 8 <= N <= 2048.
@@ -153,7 +201,7 @@ constexpr Plan make_plan(int N, int R) {
         pow2 /= big;
         ++nbig;
     }
-    int rem = pow2;  // 1, 2 or 4
+    int rem = pow2;  // 1, 2, 4 (or 8 with radix-16 passes)
     // first a big radix, then the odd factors, then the remaining big radices
     if (nbig > 0) {
         p.r[p.np++] = big;
@@ -202,14 +250,26 @@ __device__ __forceinline__ void line_sync() {
     }
 }
 
-// Number of twiddles a radix-r butterfly reads: radix 8 reads w, w^2, w^4 and forms the rest by at
-// most two products; radix 4 reads w, w^2; radix 2 and 3 read w^q, q = 1..r-1, directly.
-constexpr int tw_reads(int r) { return r == 8 ? 3 : (r == 4 ? 2 : r - 1); }
+// Number of twiddles a radix-r butterfly reads: radix 16 reads w, w^2, w^4, w^8 and forms the rest
+// by at most two products; radix 8 reads w, w^2, w^4 and forms the rest by at most two products;
+// radix 4 reads w, w^2; radix 2 and 3 read w^q, q = 1..r-1, directly.
+constexpr int tw_reads(int r) { return r == 16 ? 4 : (r == 8 ? 3 : (r == 4 ? 2 : r - 1)); }
 
 // Twiddles w^q, q = 1..r-1, of one butterfly from its tw_reads(r) loaded values.
 template <typename T, int r>
 __device__ __forceinline__ void twiddle_powers(const cpx<T>* b, cpx<T>* w) {
-    if constexpr (r == 8) {
+    if constexpr (r == 16) {
+        w[1] = b[0];
+        w[2] = b[1];
+        w[4] = b[2];
+        w[8] = b[3];
+        w[3] = cmul(w[1], w[2]);
+        w[5] = cmul(w[4], w[1]);
+        w[6] = cmul(w[4], w[2]);
+        w[7] = cmul(w[4], w[3]);
+#pragma unroll
+        for (int q = 1; q < 8; ++q) w[8 + q] = cmul(w[8], w[q]);
+    } else if constexpr (r == 8) {
         w[1] = b[0];
         w[2] = b[1];
         w[4] = b[2];
@@ -230,7 +290,12 @@ __device__ __forceinline__ void twiddle_powers(const cpx<T>* b, cpx<T>* w) {
 // The tw_reads(r) table values of a butterfly with base index `step`.
 template <typename T, int r>
 __device__ __forceinline__ void tw_fetch(twptr<T> table, int step, cpx<T>* d) {
-    if constexpr (r == 8) {
+    if constexpr (r == 16) {
+        d[0] = ldc(table, step);
+        d[1] = ldc(table, 2 * step);
+        d[2] = ldc(table, 4 * step);
+        d[3] = ldc(table, 8 * step);
+    } else if constexpr (r == 8) {
         d[0] = ldc(table, step);
         d[1] = ldc(table, 2 * step);
         d[2] = ldc(table, 4 * step);

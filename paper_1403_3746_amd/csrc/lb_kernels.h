@@ -57,9 +57,9 @@ namespace lbfft {
 // from L2.
 // LDS: x blocks (lanes of one line adjacent) store each line contiguously; y blocks (lanes of
 // neighbouring lines adjacent) interleave their lines word by word (LS = LPW).
-template <typename T, int N, int DIR, int LPW_OVERRIDE = 0, int MAXT = LB_YMAX_THREADS>
+template <typename T, int N, int DIR, int LPW_OVERRIDE = 0, int MAXT = LB_YMAX_THREADS, int RR = 0>
 struct LineCfg {
-    static constexpr int R = default_R(N);
+    static constexpr int R = RR ? RR : default_R(N);   // elements per thread
     static constexpr int TPL = N / R;
     static constexpr int CB = 2 * (int)sizeof(T);  // bytes of one complex word
     static constexpr int at_least(int l, int lo) { return l < lo ? lo : l; }
@@ -80,15 +80,20 @@ struct LineCfg {
     __device__ __forceinline__ static int lds_base(int l) { return DIR == 0 ? l * lds_line(N) : l; }
 };
 
-// The wide y-tile variant of the population y pass (blocks of up to LB_YMAX_THREADS_WIDE threads)
-// exists where it holds more column pairs than the default one for lines of N points, and in FP32
-// only: a 1024-thread block leaves 128 registers per thread, which the FP64 pass (and the
-// macroscopic passes in either precision) exceed -- they would spill.
+// Launch-plan variants of the y passes that the tuner may pick per size class (FP32 only: a
+// 1024-thread block leaves 128 registers per thread, which the FP64 passes exceed):
+//   wide: the population y pass in blocks of up to LB_YMAX_THREADS_WIDE threads, where that holds
+//         more column pairs than the default (the macroscopic passes would spill);
+//   r16:  lines of 1024 and 2048 points held 16 elements per thread (radix-16 passes): half the
+//         threads per line, so a block of up to 512 threads holds twice the column pairs.
 template <typename T, int N>
 constexpr bool pop_y_wide_exists() {
-    return sizeof(T) == 4 &&
+    // lines of 3 * 2^a points hold 12 elements per thread and would spill at 1024 threads
+    return sizeof(T) == 4 && default_R(N) == 8 &&
            LineCfg<T, N, 1, 0, LB_YMAX_THREADS_WIDE>::LPW != LineCfg<T, N, 1, 0, LB_YMAX_THREADS>::LPW;
 }
+template <typename T, int N>
+constexpr bool r16_exists() { return sizeof(T) == 4 && (N == 1024 || N == 2048); }
 
 __device__ __forceinline__ BlockWork decode_block(int ngroups, int ntiles, int njobs) {
     return decode_block_at(blockIdx.x, ngroups, ntiles, njobs);
@@ -235,12 +240,12 @@ template <typename T>
 __host__ __device__ constexpr int macro_jobs() { return sizeof(T) == 8 ? LB_MACRO_JOBS_F64 : LB_MACRO_JOBS_F32; }
 __host__ __device__ constexpr int job_slots(int njobs, int Q) { return (njobs + Q - 1) / Q; }
 
-template <typename T, int N, int DIR, int LPW_, int Q = macro_jobs<T>()>
+template <typename T, int N, int DIR, int LPW_, int RR = 0, int Q = macro_jobs<T>()>
 __device__ __forceinline__ void macro_body(int b, const InstDesc* __restrict__ insts,
                                            const int* __restrict__ ilist, int ngroups, int ntiles,
                                            const JobDesc* __restrict__ jobs, int njobs,
                                            cpx<T>* lds_all) {
-    using C = LineCfg<T, N, DIR, LPW_>;
+    using C = LineCfg<T, N, DIR, LPW_, LB_YMAX_THREADS, RR>;
     // x blocks whose lines fit in a wave synchronise per wave (line_sync)
     constexpr bool WAVE = DIR == 0 && C::TPL <= 64 && LB_WAVE_SYNC_X;
     using FFT = LineFFT<T, N, C::R, false, C::LS, WAVE>;
@@ -327,39 +332,40 @@ __device__ __forceinline__ void macro_body(int b, const InstDesc* __restrict__ i
     }
 }
 
-template <typename T, int N, int DIR>
-__global__ void __launch_bounds__((LineCfg<T, N, DIR>::WG))
+template <typename T, int N, int DIR, int RR = 0>
+__global__ void __launch_bounds__((LineCfg<T, N, DIR, 0, LB_YMAX_THREADS, RR>::WG))
 macro_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, int ngroups,
            int ntiles, const JobDesc* __restrict__ jobs, int njobs) {
-    using C = LineCfg<T, N, DIR>;
+    using C = LineCfg<T, N, DIR, 0, LB_YMAX_THREADS, RR>;
     __shared__ cpx<T> lds_all[C::LDS];
-    macro_body<T, N, DIR, C::LPW>(blockIdx.x, insts, ilist, ngroups, ntiles, jobs, njobs, lds_all);
+    macro_body<T, N, DIR, C::LPW, RR>(blockIdx.x, insts, ilist, ngroups, ntiles, jobs, njobs, lds_all);
 }
 
 // The x and y macroscopic passes of one stage of a square grid in one launch: the two read the
 // same moments and write different fields, so their blocks can run side by side.  Blocks below
 // nbx take x tiles, the rest y tiles; both use the y pass's block shape (x tiles of as many lines).
-template <typename T, int N>
+template <typename T, int N, int RR = 0>
 struct MacroXY {
-    static constexpr int LPW = LineCfg<T, N, 1>::LPW;
-    static constexpr int WG = LineCfg<T, N, 1>::WG;
-    static constexpr int LDS = LineCfg<T, N, 1>::LDS;
-    static_assert(LineCfg<T, N, 0, LPW>::WG == WG && LineCfg<T, N, 0, LPW>::LDS == LDS,
-                  "x and y tiles of the fused pass must have one block shape");
+    using Y = LineCfg<T, N, 1, 0, LB_YMAX_THREADS, RR>;
+    using X = LineCfg<T, N, 0, Y::LPW, LB_YMAX_THREADS, RR>;
+    static constexpr int LPW = Y::LPW;
+    static constexpr int WG = Y::WG;
+    static constexpr int LDS = Y::LDS;
+    static_assert(X::WG == WG && X::LDS == LDS, "x and y tiles of the fused pass must have one block shape");
 };
 
-template <typename T, int N>
-__global__ void __launch_bounds__((MacroXY<T, N>::WG))
+template <typename T, int N, int RR = 0>
+__global__ void __launch_bounds__((MacroXY<T, N, RR>::WG))
 macro_xy_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, int nbx,
               int ngroups_x, int ntiles_x, const JobDesc* __restrict__ jobs_x, int njobs_x,
               int ngroups_y, int ntiles_y, const JobDesc* __restrict__ jobs_y, int njobs_y) {
-    using M = MacroXY<T, N>;
+    using M = MacroXY<T, N, RR>;
     __shared__ cpx<T> lds_all[M::LDS];
     const int b = blockIdx.x;
     if (b < nbx)
-        macro_body<T, N, 0, M::LPW>(b, insts, ilist, ngroups_x, ntiles_x, jobs_x, njobs_x, lds_all);
+        macro_body<T, N, 0, M::LPW, RR>(b, insts, ilist, ngroups_x, ntiles_x, jobs_x, njobs_x, lds_all);
     else
-        macro_body<T, N, 1, M::LPW>(b - nbx, insts, ilist, ngroups_y, ntiles_y, jobs_y, njobs_y, lds_all);
+        macro_body<T, N, 1, M::LPW, RR>(b - nbx, insts, ilist, ngroups_y, ntiles_y, jobs_y, njobs_y, lds_all);
 }
 
 // ---------------------------------------------------------------------------------------
@@ -693,12 +699,12 @@ pop_x_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
 
 // Population y pass: one block = (instance, tile of column pairs, population i with v_y != 0).
 //   out = partial - c v_y D_y f
-template <typename T, int N, int MAXT = LB_YMAX_THREADS>
-__global__ void __launch_bounds__((LineCfg<T, N, 1, 0, MAXT>::WG))
+template <typename T, int N, int MAXT = LB_YMAX_THREADS, int RR = 0>
+__global__ void __launch_bounds__((LineCfg<T, N, 1, 0, MAXT, RR>::WG))
 pop_y_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, int ngroups,
            int ntiles, const DvmConst<T>* __restrict__ dvm, const int* __restrict__ pops, int npops,
            StageArgs st) {
-    using C = LineCfg<T, N, 1, 0, MAXT>;
+    using C = LineCfg<T, N, 1, 0, MAXT, RR>;
     constexpr int R = C::R, TPL = C::TPL, LPW = C::LPW;
     __shared__ cpx<T> lds_all[C::LDS];
     const BlockWork w = LB_JOBMAJOR_Y ? decode_block_jm(blockIdx.x, ngroups, ntiles, npops)

@@ -18,9 +18,9 @@ struct LaunchSet {
     // when set, the launch timestamps its own start and end into these events
     hipEvent_t ev_start = nullptr, ev_stop = nullptr;
     int ppb = 1;   // populations per block of the x population pass (tuned per size class)
-    // population y pass: the wide tile variant (blocks of up to LB_YMAX_THREADS_WIDE threads),
-    // tuned per size class, used where it exists
-    int ywide = 0;
+    // launch-plan variants (YVariant) of the population y pass and of the macroscopic y (or fused
+    // x + y) passes, tuned per size class; used where they exist, else the default plan
+    int ypop_var = 0, ymac_var = 0;
 };
 
 // Launch through hipExtLaunchKernelGGL when the set carries timing events.
@@ -53,10 +53,10 @@ hipError_t pop_x_f32(const LaunchSet& L, const DvmConst<float>* dvm, const DvmCo
 hipError_t pop_y_f32(const LaunchSet& L, const DvmConst<float>* dvm, const DvmConst<double>* dvm64,
                      const int* pops, int npops, StageArgs st);
 
-// Whether the population y pass of y lines of n points has the wide-tile variant
-// (lb_lines_y_<prec>.hip).
-bool wide_y_f64(int n);
-bool wide_y_f32(int n);
+// Bit set (1 << YVariant) of the launch-plan variants the y passes have for y lines of n points
+// (lb_lines_y_<prec>.hip): YV_WIDE for the population pass, YV_R16 for both.
+int variants_y_f64(int n);
+int variants_y_f32(int n);
 
 // Fused x + y macroscopic passes of square grids (lb_lines_xy_<prec>.hip).
 hipError_t macro_xy_f64(const LaunchSet& L, const JobDesc* jx, int njx, const JobDesc* jy, int njy);

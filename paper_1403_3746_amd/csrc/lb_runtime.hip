@@ -176,7 +176,7 @@ struct lb_ctx {
     struct Class {
         int nx, ny, start, count;
         int ppb = 1;   // tuned populations per block of the x population pass
-        int ywide = 0;   // tuned y tile of the population y pass (wide variant where it exists)
+        int ypop_var = 0, ymac_var = 0;   // tuned y-pass plan variants (YVariant) where they exist
         bool hist = false;   // some instance keeps a per-step conservation history
     };
     std::vector<Class> classes;
@@ -188,7 +188,8 @@ struct lb_ctx {
     int graph_steps = LB_GRAPH_STEPS;
     bool use_graph = true;
     int ppb_override = 0;   // populations per x-pass block forced by LBFFT_PPB (1, 2 or 4), else tuned
-    int ywide_override = -1;  // y tile variant forced by LBFFT_YWIDE (0 or 1), else tuned
+    int ypop_override = -1;   // population y pass variant forced by LBFFT_YPOP (0, 1, 2), else tuned
+    int ymac_override = -1;   // macroscopic y pass variant forced by LBFFT_YMAC (0, 2), else tuned
     bool fuse_xy = true;    // square grids: x and y macroscopic passes in one launch (LBFFT_FUSE_XY=0: off)
 
     template <typename Q>
@@ -255,7 +256,8 @@ void build_jobs(lb_ctx& c) {
 
 void apply_plan(const lb_ctx& c, const lb_ctx::Class& k, LaunchSet& L) {
     L.ppb = c.ppb_override ? c.ppb_override : k.ppb;
-    L.ywide = c.ywide_override >= 0 ? c.ywide_override : k.ywide;
+    L.ypop_var = c.ypop_override >= 0 ? c.ypop_override : k.ypop_var;
+    L.ymac_var = c.ymac_override >= 0 ? c.ymac_override : k.ymac_var;
 }
 
 LaunchSet set_of(const lb_ctx& c, const lb_ctx::Class& k) {
@@ -272,9 +274,9 @@ LaunchSet set_one(const lb_ctx& c, int inst, hipStream_t s) {
     return L;
 }
 
-// Whether the class's population y pass has the wide-tile variant to tune.
-bool class_has_wide(const lb_ctx& c, const lb_ctx::Class& k) {
-    return c.prec == LB_FP64 ? wide_y_f64(k.ny) : wide_y_f32(k.ny);
+// Bit set (1 << YVariant) of the y-pass plan variants the class's y lines have.
+int class_variants(const lb_ctx& c, int ny) {
+    return c.prec == LB_FP64 ? variants_y_f64(ny) : variants_y_f32(ny);
 }
 
 // The x and y macroscopic passes of a square grid run as one fused launch, issued in the x slot.
@@ -500,8 +502,9 @@ hipError_t time_candidates(const lb_ctx& c, int ncand, Launch launch, float* bes
 
 // Launch plan of one size class, measured on the class's own data with stage-1 arguments (which
 // leave the state untouched): populations per block of the x population pass (1, 2, 4), then --
-// where the class's population y pass has the wide variant -- its y tile.  Fixed choices
-// (LBFFT_PPB, LBFFT_YWIDE) are not re-tuned.
+// where the class's y lines have them -- the plan variants of the population y pass (default,
+// wide tiles, radix 16) and of the macroscopic y or fused x + y pass (default, radix 16).  Fixed
+// choices (LBFFT_PPB, LBFFT_YPOP, LBFFT_YMAC) are not re-tuned.
 hipError_t tune_class(lb_ctx& c, lb_ctx::Class& cl) {
     const bool verbose = std::getenv("LBFFT_VERBOSE") != nullptr;
     LaunchSet L = set_of(c, cl);
@@ -522,13 +525,30 @@ hipError_t tune_class(lb_ctx& c, lb_ctx::Class& cl) {
     }
     L = set_of(c, cl);
     if ((e = pop_x(c, L, st)) != hipSuccess) return e;   // the partial sums the y pass adds to
-    if (c.ywide_override < 0 && class_has_wide(c, cl)) {
-        e = time_candidates(c, 2, [&](int k) { L.ywide = k; return pop_y(c, L, st); }, ms, &best);
+    const int have = class_variants(c, cl.ny);
+    int cand[3] = {YV_DEFAULT, 0, 0}, nc = 1;
+    for (int v : {YV_WIDE, YV_R16})
+        if (have & (1 << v)) cand[nc++] = v;
+    if (c.ypop_override < 0 && nc > 1) {
+        e = time_candidates(c, nc, [&](int k) { L.ypop_var = cand[k]; return pop_y(c, L, st); }, ms, &best);
         if (e != hipSuccess) return e;
-        cl.ywide = best;
+        cl.ypop_var = cand[best];
         if (verbose)
-            std::fprintf(stderr, "lbfft tune: class %dx%d  pop y tile default %.4f wide %.4f ms\n",
-                         cl.nx, cl.ny, ms[0], ms[1]);
+            for (int k = 0; k < nc; ++k)
+                std::fprintf(stderr, "lbfft tune: class %dx%d  pop y variant %d  %.4f ms\n", cl.nx, cl.ny,
+                             cand[k], ms[k]);
+    }
+    L.ypop_var = cl.ypop_var;
+    if (c.ymac_override < 0 && (have & (1 << YV_R16))) {
+        const int mc[2] = {YV_DEFAULT, YV_R16};
+        const int kind = fused_xy(c, L) ? LB_PASS_MACRO_X1 : LB_PASS_MACRO_Y1;
+        e = time_candidates(c, 2, [&](int k) { L.ymac_var = mc[k]; return run_pass(c, L, kind, st); }, ms, &best);
+        if (e != hipSuccess) return e;
+        cl.ymac_var = mc[best];
+        if (verbose)
+            for (int k = 0; k < 2; ++k)
+                std::fprintf(stderr, "lbfft tune: class %dx%d  macro y variant %d  %.4f ms\n", cl.nx, cl.ny,
+                             mc[k], ms[k]);
     }
     return hipSuccess;
 }
@@ -702,8 +722,11 @@ lb_status lb_init(lb_ctx** out, int n_inst, const lb_params* p, const lb_dvm* dv
         const int v = std::atoi(g);
         if (v == 1 || v == 2 || v == 4) c->ppb_override = v;
     }
-    if (const char* g = std::getenv("LBFFT_YWIDE")) {
-        if (g[0] == '0' || g[0] == '1') c->ywide_override = g[0] - '0';
+    if (const char* g = std::getenv("LBFFT_YPOP")) {
+        if (g[0] >= '0' && g[0] <= '2') c->ypop_override = g[0] - '0';
+    }
+    if (const char* g = std::getenv("LBFFT_YMAC")) {
+        if (g[0] == '0' || g[0] == '2') c->ymac_override = g[0] - '0';
     }
 
     if (!build_dvm(c->dvm, c->dvm64)) {
@@ -865,7 +888,7 @@ lb_status lb_init(lb_ctx** out, int n_inst, const lb_params* p, const lb_dvm* dv
         if (!ok) break;
         const int64_t cells = (int64_t)cl.nx * cl.ny * cl.count;
         cl.ppb = cells >= (1 << 20) ? 2 : 1;   // default without tuning
-        if (tune && (!c->ppb_override || c->ywide_override < 0)) {
+        if (tune && (!c->ppb_override || c->ypop_override < 0 || c->ymac_override < 0)) {
             hipError_t e = tune_class(*c, cl);
             if (e != hipSuccess) {
                 ok = false;
@@ -1094,9 +1117,11 @@ lb_status lb_plan_info(lb_ctx* c, int inst, int* out, int n) {
     if (s != LB_OK) return s;
     if (!out || n < 2) return fail(LB_E_ARG, "need an output array of length >= 2");
     const LaunchSet L = set_one(*c, inst, c->stream);
-    const int wide = c->prec == LB_FP64 ? wide_y_f64(L.ny) : wide_y_f32(L.ny);
-    const int v[3] = {L.ppb, (int)c->classes.size(), wide && L.ywide ? 1 : 0};
-    for (int k = 0; k < n && k < 3; ++k) out[k] = v[k];
+    // the variant a launch actually runs: the chosen one where it exists for the class's y lines
+    const int have = class_variants(*c, L.ny);
+    const int v[4] = {L.ppb, (int)c->classes.size(), (have >> L.ypop_var) & 1 ? L.ypop_var : 0,
+                      (have >> L.ymac_var) & 1 ? L.ymac_var : 0};
+    for (int k = 0; k < n && k < 4; ++k) out[k] = v[k];
     return LB_OK;
 }
 

@@ -70,6 +70,10 @@ inline constexpr bool line_ok(int n) {
 }
 inline constexpr bool grid_ok(int nx, int ny) { return line_ok(nx) && (line_ok(ny) || ny == 1 || ny == 2); }
 
+// Launch-plan variants of the y passes (lb_kernels.h): the default plan, wide population y
+// tiles, radix-16 lines.
+enum YVariant : int { YV_DEFAULT = 0, YV_WIDE = 1, YV_R16 = 2 };
+
 // Conservation partial-sum blocks per instance (each block strides over the grid).
 constexpr int RED_BLOCKS = 512;
 

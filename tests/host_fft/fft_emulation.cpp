@@ -25,9 +25,9 @@ static std::vector<std::unique_ptr<std::barrier<>>> wave_barriers(int wg) {
 
 using namespace lbfft;
 
-template <typename T, int N, int LS, int LINES, int Q, bool WAVE = false>
+template <typename T, int N, int LS, int LINES, int Q, bool WAVE = false, int RR = 0>
 void run_case(const char* layout) {
-    constexpr int R = default_R(N), TPL = N / R, WG = LINES * TPL;
+    constexpr int R = RR ? RR : default_R(N), TPL = N / R, WG = LINES * TPL;
     // LDS: x blocks give line l the region l*lds_line(N) (element i at lds_idx(i)); y blocks
     // interleave the lines (element i of line l at lds_idx(i)*LINES + l)
     constexpr int STRIDE = LINES * lds_line(N);
@@ -85,7 +85,8 @@ void run_case(const char* layout) {
             nr = std::max(nr, std::abs(std::complex<double>(xi[k].re, xi[k].im)));
         }
     }
-    std::printf("%s %d %s %d %.3e %.3e\n", sizeof(T) == 8 ? "f64" : "f32", N, layout, Q, ef / nf, er / nr);
+    std::printf("%s %d %s%s %d %.3e %.3e\n", sizeof(T) == 8 ? "f64" : "f32", N, layout, RR == 16 ? "16" : "", Q,
+                ef / nf, er / nr);
 }
 
 template <typename T>
@@ -126,6 +127,13 @@ void all_sizes() {
     run_case<T, 256, 1, 4, 1, true>("xw");
     run_case<T, 512, 1, 8, 1, true>("xw");
     run_case<T, 768, 1, 2, 1, true>("xw");
+    // 16 elements per thread (radix-16 passes), the long lines' alternative plan
+    run_case<T, 512, 1, 1, 1, false, 16>("x");
+    run_case<T, 1024, 1, 1, 1, false, 16>("x");
+    run_case<T, 2048, 1, 1, 1, false, 16>("x");
+    run_case<T, 1024, 4, 4, 1, false, 16>("y");
+    run_case<T, 2048, 2, 2, 1, false, 16>("y");
+    run_case<T, 1024, 1, 2, 1, true, 16>("xw");
 }
 
 int main() {

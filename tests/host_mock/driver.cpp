@@ -38,8 +38,8 @@ int main() {
     const double* r3p[1] = {r3.data()}; const double* z3p[1] = {z3.data()}; const double* t3p[1] = {t3.data()};
     ws = lb_workspace_bytes(1, &w, LB_FP32); mem = aligned_alloc(256, ws);
     st = lb_init(&c, 1, &w, nullptr, LB_FP32, r3p, z3p, z3p, t3p, mem, ws, nullptr);
-    int plan[3] = {0, 0, -1};
-    printf("init3 %d %d\n", st, lb_plan_info(c, 0, plan, 3));
+    int plan[4] = {0, 0, -1, -1};
+    printf("init3 %d %d\n", st, lb_plan_info(c, 0, plan, 4));
     lb_step(c, 1); lb_free(c); free(mem);
     printf("done\n");
     return 0;

@@ -10,8 +10,8 @@ M(macro_x_f64, double) M(macro_y_f64, double) M(macro_x_f32, float) M(macro_y_f3
 MXY(macro_xy_f64) MXY(macro_xy_f32)
 #define P(name, T) hipError_t name(const LaunchSet& L, const DvmConst<T>* d, const DvmConst<double>* d64, const int* p, int n, StageArgs) { chk(L); assert(d && d64 && p && n > 0); return hipSuccess; }
 P(pop_x_f64, double) P(pop_y_f64, double) P(pop_x_f32, float) P(pop_y_f32, float)
-bool wide_y_f64(int) { return false; }
-bool wide_y_f32(int n) { return n >= 1024; }
+int variants_y_f64(int) { return 0; }
+int variants_y_f32(int n) { return n >= 1024 ? (1 << YV_WIDE) | (1 << YV_R16) : 0; }
 template <typename T> hipError_t launch_moments(const LaunchSet& L, const DvmConst<T>*, int) { chk(L); return hipSuccess; }
 template <typename T> hipError_t launch_stress(const LaunchSet& L) { chk(L); return hipSuccess; }
 template <typename T> hipError_t launch_finalize(const LaunchSet& L) { chk(L); return hipSuccess; }

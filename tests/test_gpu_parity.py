@@ -294,25 +294,27 @@ def test_full_step_square_sizes_of_three_times_pow2(torch_cuda, monkeypatch, ppb
         sim.close()
 
 
-@pytest.mark.parametrize("prec,ywide", [("fp64", "0"), ("fp32", "0"), ("fp32", "1")])
-def test_step_long_columns(torch_cuda, monkeypatch, prec, ywide):
+@pytest.mark.parametrize("prec,ypop,ymac", [("fp64", "0", "0"), ("fp32", "0", "0"), ("fp32", "1", "0"),
+                                           ("fp32", "2", "2")])
+def test_step_long_columns(torch_cuda, monkeypatch, prec, ypop, ymac):
     # tall grids: y lines of 768..2048 points (narrow column-pair tiles, blocks in job-major
     # order), with the last tile partly empty where nx/2 is not a multiple of the tile width; in
-    # FP32 with the default and with the wide population y tiles
-    monkeypatch.setenv("LBFFT_YWIDE", ywide)
+    # FP32 with each y-pass plan: default, wide population y tiles, radix-16 y passes
+    monkeypatch.setenv("LBFFT_YPOP", ypop)
+    monkeypatch.setenv("LBFFT_YMAC", ymac)
     tol = 1e-12 if prec == "fp64" else 2e-6
     for ny, nx in ((768, 24), (1024, 24), (1536, 12), (2048, 12)):
         p = W.base_params(q=-0.004, zeta=1e-3)
         ic = W.smooth_random(nx, ny, 7 + ny, T0=0.52)
         sim = _sim([(p, ic)], prec)
-        if prec == "fp32" and ny >= 1024:
-            assert sim.plan(0)["pop_y_wide"] == int(ywide)
+        if prec == "fp32" and ny in (1024, 2048):
+            assert sim.plan(0)["pop_y_plan"] == int(ypop) and sim.plan(0)["macro_y_plan"] == int(ymac)
         f_ref = model.init_equilibrium(*ic, p)
         for _ in range(3):
             f_ref = model.rk2_step(f_ref, p)
         sim.step(3)
         errs = field_errors(sim.get_f(), f_ref, _moments(p))
-        say(f"long columns {nx}x{ny} {prec} wide {ywide} step 3: {errs}")
+        say(f"long columns {nx}x{ny} {prec} y plans {ypop}/{ymac} step 3: {errs}")
         assert max(errs.values()) < tol, (ny, nx, errs)
         sim.close()
 
@@ -357,6 +359,28 @@ def test_ragged_multi_step_graph_matches_single_step_replays(torch_cuda, monkeyp
         assert out["1"][h][0] == out["16"][h][0]
         assert np.array_equal(out["1"][h][1], out["16"][h][1])
     assert out["16"][1][1].shape == (37, 4) and out["16"][2][0] == 0
+
+
+@pytest.mark.parametrize("ymac", ["0", "2"])
+def test_fused_square_1024_fp32_every_y_plan(torch_cuda, monkeypatch, ymac):
+    # a square grid of 1024-point lines: the fused x + y macroscopic pass with the default and the
+    # radix-16 plan (its x tiles then hold 16 elements per thread too), against the oracle
+    monkeypatch.setenv("LBFFT_YMAC", ymac)
+    monkeypatch.setenv("LBFFT_YPOP", "2" if ymac == "2" else "0")
+    n = 1024
+    p = W.base_params(q=-0.004, zeta=1e-3)
+    ic = W.smooth_random(n, n, 77, T0=0.52)
+    from tests.oracle_pool import oracle_workers
+    spectral.set_workers(oracle_workers())
+    f = model.rk2_step(model.init_equilibrium(*ic, p), p)
+    spectral.set_workers(1)
+    sim = _sim([(p, ic)], "fp32")
+    assert sim.plan(0)["macro_y_plan"] == int(ymac)
+    sim.step(1)
+    errs = field_errors(sim.get_f(), f, _moments(p))
+    say(f"square 1024 fp32 macro y plan {ymac}: {errs}")
+    assert errs["rho"] < 2e-6 and errs["T"] < 2e-6
+    sim.close()
 
 
 @pytest.mark.parametrize("ppb", ["1", "2", "4"])
