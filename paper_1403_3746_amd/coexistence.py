@@ -36,6 +36,11 @@ PAPER_PARAMS = dict(dx=0.02, dt=5e-5, tau=1e-4, K=1e-5, H=0.0, zeta=0.0, q=-0.00
 COEX_DVM = dict(va=1.15, vb=0.575, vc=2.3, vd=1.15, eta0=2.5)
 
 
+def scaled_rings(scale, eta0=2.5):
+    """The default ring speeds (1, 0.5, 2, 1) times `scale` (COEX_DVM is scale 1.15)."""
+    return dict(va=scale, vb=0.5 * scale, vc=2.0 * scale, vd=scale, eta0=eta0)
+
+
 def slab(nx=512, ny=2, rho_v=0.955, rho_l=1.045, T0=0.9975):
     """Sec. 3.1 initial state: vapour for j <= nx/4 and j > 3nx/4, liquid between, at rest."""
     j = np.arange(nx)
@@ -136,11 +141,13 @@ def main(argv=None):
     ap.add_argument("--K", type=float, default=PAPER_PARAMS["K"],
                     help="surface-tension coefficient (the Sec. 3.1 value by default)")
     ap.add_argument("--nx", type=int, default=512)
+    ap.add_argument("--ring-scale", type=float, default=1.15,
+                    help="ring speeds (1, 0.5, 2, 1) times this factor (the paper does not print them)")
     ap.add_argument("--json", help="write the records here")
     a = ap.parse_args(argv)
     recs = run(a.temperatures, a.precision, nx=a.nx, check=a.check, window=a.window, tol=a.tol,
                max_steps=a.max_steps, hold=not a.no_hold, params=dict(K=a.K),
-               log=lambda s: print(s, flush=True))
+               dvm=scaled_rings(a.ring_scale), log=lambda s: print(s, flush=True))
     for r in recs:
         print(json.dumps(r), flush=True)
     if a.json:

@@ -84,3 +84,10 @@ def test_run_schedule_with_stand_in(monkeypatch, hold):
         assert recs[1]["T_mean"] > 0.9 + 2e-3
     for r in recs:
         assert r["rho_l"] > r["rho_v"] and r["steps"] % 1000 == 0
+
+
+def test_scaled_rings_match_the_default_set():
+    from paper_1403_3746_amd import coexistence as C
+    assert C.scaled_rings(1.15) == C.COEX_DVM
+    d = C.scaled_rings(2.0)
+    assert (d["va"], d["vb"], d["vc"], d["vd"], d["eta0"]) == (2.0, 1.0, 4.0, 2.0, 2.5)
