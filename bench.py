@@ -98,7 +98,7 @@ def run_gpu(instances, precision, steps, warmup, timed_steps, settle=None):
     sim = Sim(instances, precision)
     cells = sum(ic[0].size for _, ic in instances)
     if settle is not None:
-        settle()      # GPU clocks up again after the context's set-up, before its warm-up steps
+        settle(sim)   # GPU clocks up again after the context's set-up, before its warm-up steps
     sim.step(warmup)
     sim.sync()
     torch.cuda.synchronize()
@@ -119,10 +119,19 @@ def run_gpu(instances, precision, steps, warmup, timed_steps, settle=None):
                 passes=passes, plan=plan)
 
 
+def spin(sim, seconds):
+    """Step `sim` untimed for about `seconds` of wall time: a GPU that has just come out of idle (or
+    has sat through a context's set-up on the host) runs its first tenths of a second a few per
+    cent slower than at its settled clocks."""
+    t0 = time.perf_counter()
+    while time.perf_counter() - t0 < seconds:
+        sim.step(64)
+        sim.sync()
+    return time.perf_counter() - t0
+
+
 class GpuWarmer:
-    """A throwaway 512x512 FP64 context stepped untimed for a given wall time right before a timed
-    region: a GPU that has just come out of idle (or has sat through a context's set-up on the
-    host) runs its first tenths of a second a few per cent slower than at its settled clocks."""
+    """A throwaway 512x512 FP64 context stepped untimed right before each timed run."""
 
     def __init__(self):
         from paper_1403_3746_amd import workloads as W
@@ -133,11 +142,7 @@ class GpuWarmer:
         self.total = 0.0
 
     def spin(self, seconds):
-        t0 = time.perf_counter()
-        while time.perf_counter() - t0 < seconds:
-            self.sim.step(64)
-            self.sim.sync()
-        self.total += time.perf_counter() - t0
+        self.total += spin(self.sim, seconds)
 
     def close(self):
         self.sim.close()
@@ -264,9 +269,12 @@ def main():
     from paper_1403_3746_amd import workloads as W
 
     if args.only:
+        # profiling runs: the measured context itself is stepped untimed first, so that the
+        # profiler sees only this workload's kernels, at settled clocks
         name, prec = args.only.rsplit("_", 1)
         insts, _ = W.config(name)
-        r = run_gpu(insts, prec, args.steps, args.warmup, args.timed_steps)
+        settle = (lambda sim: spin(sim, args.gpu_warm)) if args.gpu_warm > 0 else None
+        r = run_gpu(insts, prec, args.steps, args.warmup, args.timed_steps, settle)
         print(json.dumps({"workload": args.only, "mlups": round(r["mlups"], 2),
                           "ms_per_step": round(r["ms_per_step"], 5), "plan": r["plan"],
                           "roofline": roofline(r, 8 if prec == "fp64" else 4, args.only)}))
@@ -278,7 +286,7 @@ def main():
     # every timed run starts on a GPU at its settled clocks (the variants also run before the
     # headline), so that a short timed region measures the steady rate of a long run
     warmer = GpuWarmer() if args.gpu_warm > 0 else None
-    settle = (lambda: warmer.spin(args.gpu_warm)) if warmer else None
+    settle = (lambda sim: warmer.spin(args.gpu_warm)) if warmer else None
     var, rb = {}, None
     if not args.no_variants:
 
