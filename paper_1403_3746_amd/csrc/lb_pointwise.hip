@@ -43,24 +43,40 @@ tables_kernel(const InstDesc* __restrict__ insts, int inst) {
     }
 }
 
-// Final sum of the block partials in a fixed order (one block per instance, one thread per
-// quantity): cons = sums times dx^2 (the non-finite count unscaled); with record != 0 the four
-// integrals are also appended to the history ring buffer.
-__global__ void __launch_bounds__(64)
+// Final sum of the block partials in a fixed order (one block per instance): each thread adds
+// RED_BLOCKS / 256 partials of each quantity, then a pairwise tree in LDS -- the same order in every
+// call, so the sums are reproducible.  cons = sums times dx^2 (the non-finite count unscaled); with
+// record != 0 the four integrals are also appended to the history ring buffer.
+constexpr int FINAL_THREADS = 256;
+static_assert(RED_BLOCKS % FINAL_THREADS == 0, "partials per thread");
+
+__global__ void __launch_bounds__(FINAL_THREADS)
 conserve_final(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, int record) {
     const InstDesc& I = insts[ilist[blockIdx.x]];
-    const int k = threadIdx.x;
-    double s = 0.0;
-    if (k < 5)
-        for (int b = 0; b < I.red_blocks; ++b) s += I.red[b * 5 + k];
+    const int t = threadIdx.x;
+    __shared__ double sh[5][FINAL_THREADS];
+    double acc[5] = {0, 0, 0, 0, 0};
+    for (int b = t; b < I.red_blocks; b += FINAL_THREADS) {
+#pragma unroll
+        for (int k = 0; k < 5; ++k) acc[k] += I.red[b * 5 + k];
+    }
+#pragma unroll
+    for (int k = 0; k < 5; ++k) sh[k][t] = acc[k];
+    __syncthreads();
+    for (int s = FINAL_THREADS / 2; s > 0; s >>= 1) {
+        if (t < s) {
+#pragma unroll
+            for (int k = 0; k < 5; ++k) sh[k][t] += sh[k][t + s];
+        }
+        __syncthreads();
+    }
     const double area = I.dx * I.dx;
-    if (k < 5) I.cons[k] = k < 4 ? s * area : s;
+    if (t < 5) I.cons[t] = t < 4 ? sh[t][0] * area : sh[t][0];
     if (record && I.hist_len > 0) {
-        __syncthreads();
         const unsigned long long n = *I.hist_count;
-        if (k < 4) I.hist[(n % (unsigned long long)I.hist_len) * 4 + k] = s * area;
-        __syncthreads();
-        if (k == 0) *I.hist_count = n + 1;
+        __syncthreads();   // every thread has read the count before thread 0 advances it
+        if (t < 4) I.hist[(n % (unsigned long long)I.hist_len) * 4 + t] = sh[t][0] * area;
+        if (t == 0) *I.hist_count = n + 1;
     }
 }
 
@@ -109,7 +125,7 @@ hipError_t launch_conserve(const LaunchSet& L, int record) {
                        L.insts, L.ilist);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(conserve_final, dim3(L.ninst), dim3(64), 0, L.stream, L.insts, L.ilist, record);
+    hipLaunchKernelGGL(conserve_final, dim3(L.ninst), dim3(FINAL_THREADS), 0, L.stream, L.insts, L.ilist, record);
     return hipGetLastError();
 }
 
