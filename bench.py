@@ -303,7 +303,7 @@ def main():
                                                max(1, args.timed_steps // 4))
         # the large single domain with its per-step FP64 conservation history, and the ragged batch
         # (fewer steps: each step is 8-16x the work of the headline's)
-        big_steps, big_warm = max(1, args.steps // 8), max(1, args.warmup // 4)
+        big_steps, big_warm = max(10, args.steps // 8), max(2, args.warmup // 4)
         _, var["quench2048_fp32"] = variant("quench2048", "fp32", big_steps, big_warm, 2)
         _, var["ragged64_fp32"] = variant("ragged64", "fp32", big_steps, big_warm, 2)
     main_res = run_gpu(insts, "fp64", args.steps, args.warmup, args.timed_steps, settle)
