@@ -493,6 +493,7 @@ struct PopXEpi {
     E b;
     T c, ct;     // c = alpha dt; ct = c / tau, the same value as in the spectral loss term
     const E (&fref)[P];   // reference populations of the block's P populations (the state is f - fref)
+    E Tref;      // reference temperature (the temperature field holds T - Tref)
 
     __device__ __forceinline__ uint32_t cell(int k) const {
         const int m = k >> 1, h = k & 1;
@@ -520,7 +521,9 @@ struct PopXEpi {
             for (int j = 0; j < G; ++j) {
                 const int k = g * G + j, m = k >> 1, h = k & 1;
                 const T* x = v[g & 1][j];
-                const T rho = x[0], ux = x[1], uy = x[2], Tm = x[3], Bx = x[4], By = x[5], Dc = x[6];
+                const T rho = x[0], ux = x[1], uy = x[2], Bx = x[4], By = x[5], Dc = x[6];
+                const E TmE = Tref + E(x[3]);
+                const T Tm = T(TmE);
                 E mq[16];
                 // BGK gain and forcing: f^eq/tau + I = f^eq [1/tau - A - B.(v - u) - D |v - u|^2]
                 // with A = -2 D T; the force part expanded in v: h0 + hx v_x + hy v_y + hv |v|^2.
@@ -530,10 +533,10 @@ struct PopXEpi {
                 const T hx = T(2) * Dc * ux - Bx, hy = T(2) * Dc * uy - By, hv = -Dc;
                 E fe[P];
                 if constexpr (P == 1) {
-                    meq_unit<E>(E(ux), E(uy), E(Tm), b, mq);
+                    meq_unit<E>(E(ux), E(uy), TmE, b, mq);
                     fe[0] = feq_dot(DE, pop[0], E(rho), mq);
                 } else {
-                    meq_unit<E>(E(rotu ? uy : ux), E(rotu ? -ux : uy), E(Tm), b, mq);
+                    meq_unit<E>(E(rotu ? uy : ux), E(rotu ? -ux : uy), TmE, b, mq);
 #pragma unroll
                     for (int q = 0; q < P; q += 2)
                         feq_mirror_pair<E, 0>(DE, rotu ? D.rot[pop[q]] : pop[q], E(rho), mq, fe[q], fe[q + 1]);
@@ -625,7 +628,7 @@ pop_x_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
 #pragma unroll
     for (int q = 0; q < P; ++q) fref[q] = EqT<T>(I.fref[pop[q]]);
     const PopXEpi<T, R, TPL, P> epi{D, eq_table(dvm, dvm64), pop, arena<T>(I), cf, basep, outp, has_base,
-                                    line, t, nx, row1, EqT<T>(I.b), c, ct, fref};
+                                    line, t, nx, row1, EqT<T>(I.b), c, ct, fref, EqT<T>(I.T_ref)};
     using Epi = PopXEpi<T, R, TPL, P>;
     T ev[2][Epi::G][Epi::NV];
     // FP64, P > 1: the first group of epilogue inputs is requested before the transforms (its latency
@@ -766,27 +769,29 @@ pop_y_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
 template <typename T>
 __global__ void __launch_bounds__(256)
 moments_kernel(const InstDesc* __restrict__ insts, const int* __restrict__ ilist,
-               const DvmConst<T>* __restrict__ dvm, int f_field) {
+               const DvmConst<double>* __restrict__ dvm, int f_field) {
     LB_POINTWISE_PROLOGUE
-    const DvmConst<T>& D = *dvm;
-    // the stored state is f - fref: its moments plus those of the reference (whose momentum
-    // vanishes: the reference is at rest)
-    T r = 0, jx = 0, jy = 0, en = 0;
+    const DvmConst<double>& D = *dvm;
+    // in float64 whatever the stored precision, rounded once on store.  The stored state is
+    // f - fref: its moments plus those of the reference, which is at rest with density rho_ref
+    // and energy moment e_ref = rho_ref b T_ref.  The temperature is stored as T - T_ref =
+    // ((E - rho b T_ref) / rho - |u|^2) / b, where E - rho b T_ref = en - r b T_ref in terms of the
+    // deviations' own moments r, en, so that its rounding scales with the deviation.
+    double r = 0, jx = 0, jy = 0, en = 0;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-        const T f = fieldp<T>(I, f_field + i)[e];
+        const double f = fieldp<T>(I, f_field + i)[e];
         r += f;
         jx += f * D.vx[i];
         jy += f * D.vy[i];
         en += f * D.w[i];
     }
-    r = T(I.rho_ref) + r;
-    en = T(I.e_ref) + en;
-    const T ux = jx / r, uy = jy / r;
-    fieldp<T>(I, RHO)[e] = r;
-    fieldp<T>(I, UX)[e] = ux;
-    fieldp<T>(I, UY)[e] = uy;
-    fieldp<T>(I, TT)[e] = (en / r - ux * ux - uy * uy) / T(I.b);
+    const double rho = I.rho_ref + r;
+    const double ux = jx / rho, uy = jy / rho;
+    fieldp<T>(I, RHO)[e] = T(rho);
+    fieldp<T>(I, UX)[e] = T(ux);
+    fieldp<T>(I, UY)[e] = T(uy);
+    fieldp<T>(I, TT)[e] = T(((en - r * I.bT_ref) / rho - ux * ux - uy * uy) / I.b);
 }
 
 // Stress S = (P^w - rho T) I + Lambda - zeta (div u) I, div u, Q = q rho T grad T and the part
@@ -796,7 +801,7 @@ template <typename T>
 __global__ void __launch_bounds__(256)
 stress_kernel(const InstDesc* __restrict__ insts, const int* __restrict__ ilist) {
     LB_POINTWISE_PROLOGUE
-    const T rho = fieldp<T>(I, RHO)[e], Tm = fieldp<T>(I, TT)[e];
+    const T rho = fieldp<T>(I, RHO)[e], Tm = T(I.T_ref) + fieldp<T>(I, TT)[e];   // field: T - T_ref
     const T rx = fieldp<T>(I, RX)[e], ry = fieldp<T>(I, RY)[e];
     const T lap = fieldp<T>(I, RXX)[e] + fieldp<T>(I, RYY)[e];
     const T Tx = fieldp<T>(I, TX)[e], Ty = fieldp<T>(I, TY)[e];
@@ -836,7 +841,7 @@ template <typename T>
 __global__ void __launch_bounds__(256)
 finalize_kernel(const InstDesc* __restrict__ insts, const int* __restrict__ ilist) {
     LB_POINTWISE_PROLOGUE
-    const T rho = fieldp<T>(I, RHO)[e], Tm = fieldp<T>(I, TT)[e];
+    const T rho = fieldp<T>(I, RHO)[e], Tm = T(I.T_ref) + fieldp<T>(I, TT)[e];   // field: T - T_ref
     const T rT = rho * Tm;
     fieldp<T>(I, BX)[e] = (fieldp<T>(I, DSXX)[e] + fieldp<T>(I, DYSXY)[e]) / rT;
     fieldp<T>(I, BY)[e] = (fieldp<T>(I, DSXY)[e] + fieldp<T>(I, DYSYY)[e]) / rT;
@@ -880,7 +885,7 @@ conserve_partial(const InstDesc* __restrict__ insts, const int* __restrict__ ili
     const LB_GLOBAL T* gxp = fieldp<T>(I, RX);
     const LB_GLOBAL T* gyp = fieldp<T>(I, RY);
     for (uint32_t e = blockIdx.x * blockDim.x + threadIdx.x; e < nc; e += I.red_blocks * blockDim.x) {
-        const double rho = rp[e], ux = xp[e], uy = yp[e], Tm = tp[e], rx = gxp[e], ry = gyp[e];
+        const double rho = rp[e], ux = xp[e], uy = yp[e], Tm = I.T_ref + tp[e], rx = gxp[e], ry = gyp[e];
         const double en = 0.5 * rho * (I.b * Tm + ux * ux + uy * uy) - I.a * rho * rho +
                           0.5 * I.K * (rx * rx + ry * ry);
         acc[0] += rho;

@@ -64,7 +64,7 @@ hipError_t macro_xy_f32(const LaunchSet& L, const JobDesc* jx, int njx, const Jo
 
 // Pointwise kernels (lb_pointwise.hip).
 template <typename T>
-hipError_t launch_moments(const LaunchSet& L, const DvmConst<T>* dvm, int f_field);
+hipError_t launch_moments(const LaunchSet& L, const DvmConst<double>* dvm, int f_field);
 template <typename T>
 hipError_t launch_stress(const LaunchSet& L);
 template <typename T>

@@ -83,7 +83,7 @@ conserve_final(const InstDesc* __restrict__ insts, const int* __restrict__ ilist
 }  // namespace
 
 template <typename T>
-hipError_t launch_moments(const LaunchSet& L, const DvmConst<T>* dvm, int f_field) {
+hipError_t launch_moments(const LaunchSet& L, const DvmConst<double>* dvm, int f_field) {
     const int64_t nc = (int64_t)L.nx * L.ny;
     LB_LAUNCH(L, (moments_kernel<T>), cell_grid(nc, L.ninst), dim3(256), L.insts, L.ilist, dvm,
               f_field);
@@ -144,7 +144,7 @@ hipError_t launch_from_f64(const double* src, void* dst, int64_t n, hipStream_t 
 }
 
 #define LB_INST(T)                                                                         \
-    template hipError_t launch_moments<T>(const LaunchSet&, const DvmConst<T>*, int);      \
+    template hipError_t launch_moments<T>(const LaunchSet&, const DvmConst<double>*, int); \
     template hipError_t launch_stress<T>(const LaunchSet&);                                \
     template hipError_t launch_finalize<T>(const LaunchSet&);                              \
     template hipError_t launch_init<T>(const LaunchSet&, const DvmConst<double>*);         \

@@ -294,8 +294,8 @@ hipError_t macro(const lb_ctx& c, const LaunchSet& L, int dir, int j0, int nj) {
 }
 
 hipError_t moments(const lb_ctx& c, const LaunchSet& L, int f_field) {
-    if (c.prec == LB_FP64) return launch_moments<double>(L, c.dev<DvmConst<double>>(c.lay.dvm64), f_field);
-    return launch_moments<float>(L, c.dev<DvmConst<float>>(c.lay.dvm32), f_field);
+    const DvmConst<double>* d64 = c.dev<DvmConst<double>>(c.lay.dvm64);
+    return c.prec == LB_FP64 ? launch_moments<double>(L, d64, f_field) : launch_moments<float>(L, d64, f_field);
 }
 
 hipError_t stress(const lb_ctx& c, const LaunchSet& L) {
@@ -561,7 +561,8 @@ lb_status check_inst(const lb_ctx* c, int inst) {
 
 // Reference populations of an FP32 instance (the arena stores f - fref): the equilibrium at rest of
 // the mean initial temperature and of the mean initial density rounded to float32 (so that the
-// moment kernel adds an exact rho_ref), in float64 (Sec. 2.1, seven kinetic moments at u = 0).
+// moment kernel adds an exact rho_ref), in float64 (Sec. 2.1, seven kinetic moments at u = 0); and
+// the reference's own temperature, from which the temperature field is stored as a deviation.
 void set_reference(const DvmConst<double>& D, const lb_params& q, const double* rho0, const double* T0,
                    InstDesc& I) {
     const int64_t nc = (int64_t)q.nx * q.ny;
@@ -582,6 +583,8 @@ void set_reference(const DvmConst<double>& D, const lb_params& q, const double* 
         I.fref[i] = rho * s;
         I.e_ref += I.fref[i] * D.w[i];
     }
+    I.bT_ref = I.e_ref / rho;
+    I.T_ref = I.bT_ref / b;
 }
 
 // Copy field `fid` of instance inst (nc words of the working precision) to host float64.
@@ -992,6 +995,10 @@ lb_status lb_moments(lb_ctx* c, int inst, double* rho, double* ux, double* uy, d
     double* dst[4] = {rho, ux, uy, T};
     for (int f = 0; f < 4; ++f)
         if (dst[f] && (s = field_to_host(c, inst, RHO + f, dst[f])) != LB_OK) return s;
+    // the temperature field holds T - T_ref
+    const double Tref = c->hinst[inst].T_ref;
+    if (T && Tref != 0.0)
+        for (int64_t e = 0; e < c->hinst[inst].ncell; ++e) T[e] += Tref;
     LB_HIP(hipStreamSynchronize(c->stream));
     return LB_OK;
 }

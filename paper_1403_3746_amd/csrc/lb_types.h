@@ -56,9 +56,10 @@ struct InstDesc {
     // f^eq(rho_ref, 0, T_ref) of the instance's mean initial density and temperature, so that the
     // stored deviations are small and their rounding too; FP64 contexts: fref = 0, the plain f).
     // rho_ref and e_ref are the density and energy moments sum fref and sum fref (v^2 + eta^2);
-    // rho_ref is exactly representable in float32.
+    // rho_ref is exactly representable in float32.  T_ref = e_ref / (b rho_ref) is the reference's
+    // temperature, bT_ref = b T_ref: the temperature field holds T - T_ref (FP64 contexts: both 0).
     double fref[16];
-    double rho_ref, e_ref;
+    double rho_ref, e_ref, T_ref, bT_ref;
 };
 
 // Line lengths of the transforms: 2^a and 3 * 2^a from 8 to 2048.  A grid takes them along x,

@@ -12,7 +12,7 @@ MXY(macro_xy_f64) MXY(macro_xy_f32)
 P(pop_x_f64, double) P(pop_y_f64, double) P(pop_x_f32, float) P(pop_y_f32, float)
 int variants_y_f64(int) { return 0; }
 int variants_y_f32(int n) { return n >= 1024 ? (1 << YV_WIDE) | (1 << YV_R16) : 0; }
-template <typename T> hipError_t launch_moments(const LaunchSet& L, const DvmConst<T>*, int) { chk(L); return hipSuccess; }
+template <typename T> hipError_t launch_moments(const LaunchSet& L, const DvmConst<double>*, int) { chk(L); return hipSuccess; }
 template <typename T> hipError_t launch_stress(const LaunchSet& L) { chk(L); return hipSuccess; }
 template <typename T> hipError_t launch_finalize(const LaunchSet& L) { chk(L); return hipSuccess; }
 template <typename T> hipError_t launch_init(const LaunchSet& L, const DvmConst<double>*) { chk(L); return hipSuccess; }
@@ -20,7 +20,7 @@ template <typename T> hipError_t launch_tables(const InstDesc*, int, int, int, h
 template <typename T> hipError_t launch_conserve(const LaunchSet& L, int) { chk(L); return hipSuccess; }
 template <typename T> hipError_t launch_to_f64(const void*, double*, int64_t, hipStream_t) { return hipSuccess; }
 template <typename T> hipError_t launch_from_f64(const double*, void*, int64_t, hipStream_t) { return hipSuccess; }
-#define I(T) template hipError_t launch_moments<T>(const LaunchSet&, const DvmConst<T>*, int); \
+#define I(T) template hipError_t launch_moments<T>(const LaunchSet&, const DvmConst<double>*, int); \
  template hipError_t launch_stress<T>(const LaunchSet&); template hipError_t launch_finalize<T>(const LaunchSet&); \
  template hipError_t launch_init<T>(const LaunchSet&, const DvmConst<double>*); \
  template hipError_t launch_tables<T>(const InstDesc*, int, int, int, hipStream_t); \
