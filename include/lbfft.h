@@ -109,7 +109,9 @@ lb_status lb_step(lb_ctx* ctx, int n_steps);
 lb_status lb_sync(lb_ctx* ctx);
 
 /* Copy the moments (Sec. 2.1) rho = sum f, rho u = sum f v, rho (b T + u^2) = sum f (v^2 + eta^2)
- * of instance inst into host arrays [ny][nx] (any pointer may be NULL).  Synchronises. */
+ * of instance inst into host arrays [ny][nx] (any pointer may be NULL).  They are formed in
+ * float64 from the stored state; an FP32 context stores them rounded to float32 (T as its
+ * deviation from the instance's reference temperature, added back here).  Synchronises. */
 lb_status lb_moments(lb_ctx* ctx, int inst, double* rho, double* ux, double* uy, double* T);
 
 /* Grid integrals (sum over cells times dx^2), accumulated in float64 in both precisions:
