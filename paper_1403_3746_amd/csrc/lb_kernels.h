@@ -772,26 +772,27 @@ moments_kernel(const InstDesc* __restrict__ insts, const int* __restrict__ ilist
                const DvmConst<double>* __restrict__ dvm, int f_field) {
     LB_POINTWISE_PROLOGUE
     const DvmConst<double>& D = *dvm;
-    // in float64 whatever the stored precision, rounded once on store.  The stored state is
-    // f - fref: its moments plus those of the reference, which is at rest with density rho_ref
-    // and energy moment e_ref = rho_ref b T_ref.  The temperature is stored as T - T_ref =
-    // ((E - rho b T_ref) / rho - |u|^2) / b, where E - rho b T_ref = en - r b T_ref in terms of the
-    // deviations' own moments r, en, so that its rounding scales with the deviation.
-    double r = 0, jx = 0, jy = 0, en = 0;
+    // The stored state is f - fref: its moments plus those of the reference, which is at rest
+    // with density rho_ref and energy moment e_ref = rho_ref b T_ref.  The deviations' own moments
+    // r, jx, jy, en are summed in the working precision (their rounding scales with the
+    // deviation); the rest is formed in float64 and rounded once on store.  The temperature is
+    // stored as T - T_ref = ((E - rho b T_ref) / rho - |u|^2) / b, where E - rho b T_ref =
+    // en - r b T_ref.
+    T r = 0, jx = 0, jy = 0, en = 0;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-        const double f = fieldp<T>(I, f_field + i)[e];
+        const T f = fieldp<T>(I, f_field + i)[e];
         r += f;
-        jx += f * D.vx[i];
-        jy += f * D.vy[i];
-        en += f * D.w[i];
+        jx += f * T(D.vx[i]);
+        jy += f * T(D.vy[i]);
+        en += f * T(D.w[i]);
     }
-    const double rho = I.rho_ref + r;
-    const double ux = jx / rho, uy = jy / rho;
+    const double rho = I.rho_ref + double(r);
+    const double ux = double(jx) / rho, uy = double(jy) / rho;
     fieldp<T>(I, RHO)[e] = T(rho);
     fieldp<T>(I, UX)[e] = T(ux);
     fieldp<T>(I, UY)[e] = T(uy);
-    fieldp<T>(I, TT)[e] = T(((en - r * I.bT_ref) / rho - ux * ux - uy * uy) / I.b);
+    fieldp<T>(I, TT)[e] = T(((double(en) - double(r) * I.bT_ref) / rho - ux * ux - uy * uy) / I.b);
 }
 
 // Stress S = (P^w - rho T) I + Lambda - zeta (div u) I, div u, Q = q rho T grad T and the part
