@@ -1,4 +1,4 @@
-// Line FFT engine for gfx950: Stockham autosort mixed-radix (2, 3, 4, 8) transforms of complex
+// Line FFT engine for gfx950: Stockham autosort mixed-radix (2, 3, 4, 8, 12, 16) transforms of complex
 // lines of length N held R elements per thread, exchanged through LDS between passes.
 //
 // A line is processed by N/R consecutive "line threads"; thread t holds elements t + m*(N/R),
@@ -123,6 +123,30 @@ struct Dft<T, 8, INV> {
     }
 };
 
+// 12-point DFT by the Good-Thomas (prime-factor) split 12 = 3 x 4: with the input index
+// n = (4 n1 + 3 n2) mod 12 and the output index k = (4 k1 + 9 k2) mod 12 (both bijections, by the
+// Chinese remainder theorem) the kernel factors as W12^(nk) = W3^(n1 k1) W4^(n2 k2), so four
+// 3-point DFTs over n1 followed by three 4-point DFTs over n2 need no twiddles between them.
+template <typename T, bool INV>
+struct Dft<T, 12, INV> {
+    __device__ __forceinline__ static void run(cpx<T>* v) {
+        cpx<T> y[4][3];
+#pragma unroll
+        for (int n2 = 0; n2 < 4; ++n2) {
+#pragma unroll
+            for (int n1 = 0; n1 < 3; ++n1) y[n2][n1] = v[(4 * n1 + 3 * n2) % 12];
+            Dft<T, 3, INV>::run(y[n2]);
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < 3; ++k1) {
+            cpx<T> c[4] = {y[0][k1], y[1][k1], y[2][k1], y[3][k1]};
+            Dft<T, 4, INV>::run(c);
+#pragma unroll
+            for (int k2 = 0; k2 < 4; ++k2) v[(4 * k1 + 9 * k2) % 12] = c[k2];
+        }
+    }
+};
+
 // a * W16^m, W16 = exp(-+ 2 pi i / 16) (forward / inverse), for the internal twiddles of the
 // 16-point DFT (m = n2 k1 <= 9); m is a constant after unrolling, so the switch folds away and the
 // eighth and quarter turns cost no general product.
@@ -193,9 +217,21 @@ constexpr Plan make_plan(int N, int R) {
         p.r[0] = 2;
         return p;
     }
+    if (R == 12) {
+        // lines of 3 * 2^a points: one radix-12 pass straight from the registers, then the power
+        // of two N/12 in radix-4 passes (a radix-2 pass first when the exponent is odd)
+        p.r[p.np++] = 12;
+        int q = N / 12;
+        if (q > 1 && (ilog2c(q) & 1)) {
+            p.r[p.np++] = 2;
+            q /= 2;
+        }
+        for (; q > 1; q /= 4) p.r[p.np++] = 4;
+        return p;
+    }
     int three = (N % 3 == 0) ? 1 : 0;
     int pow2 = three ? N / 3 : N;
-    int big = (R == 12) ? 4 : R;
+    int big = R;
     int nbig = 0;
     while (pow2 >= big && pow2 % big == 0) {
         pow2 /= big;
@@ -229,10 +265,22 @@ __host__ __device__ constexpr int lds_line(int N) { return N + (N >> LDS_PAD_SHI
 template <typename T>
 using twptr = const LB_GLOBAL cpx<T>*;
 
-// Complex load from global memory (member-wise: no copy constructor across address spaces).
+// Bytes a table read may address: the longest line's table (2048 complex float64 words).
+constexpr int TABLE_MAX_BYTES = 2048 * 16;
+
+// Table entry idx as one load of the whole complex word (a 16-byte buffer load in float64, 8 bytes
+// in float32).  Read member by member, the two halves were separate loads that the code generator
+// pairs up again afterwards, and hipcc of ROCm 7.2 (AMD clang 22) paired them wrongly in the
+// 96-point float64 x passes: the imaginary half of one twiddle was taken from another entry's
+// load (the optimised IR was right; the emitted code was not).  One intrinsic load per entry
+// leaves nothing to pair.
 template <typename T>
 __device__ __forceinline__ cpx<T> ldc(twptr<T> p, int idx) {
-    return cpx<T>{p[idx].re, p[idx].im};
+    const __amdgpu_buffer_rsrc_t r = __builtin_amdgcn_make_buffer_rsrc((void*)p, 0, TABLE_MAX_BYTES, 0x00020000);
+    if constexpr (sizeof(T) == 8)
+        return __builtin_bit_cast(cpx<T>, __builtin_amdgcn_raw_buffer_load_b128(r, (unsigned)idx * 16u, 0, 0));
+    else
+        return __builtin_bit_cast(cpx<T>, __builtin_amdgcn_raw_buffer_load_b64(r, (unsigned)idx * 8u, 0, 0));
 }
 
 // Barrier between the LDS exchanges of a transform.  WAVE: every line the block holds belongs to
