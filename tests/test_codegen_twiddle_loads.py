@@ -18,7 +18,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 sys.path.insert(0, ROOT)
 from paper_1403_3746_amd import build as B  # noqa: E402
 
-UNITS = ["lb_lines_x_f64", "lb_lines_x_f32", "lb_lines_xy_f64", "lb_lines_xy_f32"]
+UNITS = ["lb_lines_x_f64", "lb_lines_x_f32", "lb_lines_y_f64", "lb_lines_y_f32", "lb_lines_xy_f64", "lb_lines_xy_f32"]
 LOAD = re.compile(r"global_load_dwordx(\d) (v\[\d+:\d+\]), (v\d+), (s\[\d+:\d+\])(?: offset:(\d+))?")
 
 
