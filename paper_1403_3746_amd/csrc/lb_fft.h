@@ -359,11 +359,15 @@ __device__ __forceinline__ void tw_fetch(twptr<T> table, int step, cpx<T>* d) {
 // The twiddles one thread reads over all passes of a line transform (passes after the first).
 // Pass s with Ns = r_0...r_{s-1} gives butterfly b of thread t (element j = t + b*TPL,
 // k = j mod Ns) the powers of tw[k*N/(Ns*r)].  When they fit in a few registers (COUNT complex
-// values, at most LB_TW_PRELOAD) they are loaded together up front, so their latencies overlap,
+// values, at most LB_TW_PRELOAD / LB_TW_PRELOAD_F32) they are loaded together up front, so their
+// latencies overlap,
 // and shared by the forward and inverse transforms of the line (the inverse multiplies by their
 // conjugates); otherwise each pass loads its own from the table.
 #ifndef LB_TW_PRELOAD
-#define LB_TW_PRELOAD 12
+#define LB_TW_PRELOAD 12      // float64: at most 12 complex values (48 registers)
+#endif
+#ifndef LB_TW_PRELOAD_F32
+#define LB_TW_PRELOAD_F32 18  // float32: at most 18 (36 registers; the 384- and 768-point plans)
 #endif
 template <typename T, int N, int R>
 struct TwSet {
@@ -376,7 +380,7 @@ struct TwSet {
         return o;
     }
     static constexpr int COUNT = offset(P.np);
-    static constexpr bool PRE = COUNT <= LB_TW_PRELOAD;
+    static constexpr bool PRE = COUNT <= (sizeof(T) == 4 ? LB_TW_PRELOAD_F32 : LB_TW_PRELOAD);
     cpx<T> w[PRE && COUNT > 0 ? COUNT : 1];
     twptr<T> table;
     int t;

@@ -6,10 +6,10 @@ circle at the fixed temperature T = 0.95, with dx = dy = 0.01, tau = 5 dt = 5e-4
 q = -0.05 and the paper's van der Waals fluid.  The paper does not give the domain size; here it
 is 192 x 192 cells, the droplet centred (37 cells of vapour beyond each end).  "T fixed" is read
 as the run's strong heat conduction (q = -0.05), which keeps the temperature within a few 1e-3 of
-0.95 by itself; the driver records the temperature range to show it.  (Restarting the state at
+0.95 by itself; `run` records the temperature range to show it.  (Restarting the state at
 T = 0.95 every `hold_every` steps, f = f^eq(rho, u, 0.95), is available but destabilises this
 run: it removes the non-equilibrium part of f, which carries the viscous stress.)  At every check
-the driver records the largest flow speed (the spurious velocity u_max^s once the droplet has
+`run` records the largest flow speed (the spurious velocity u_max^s once the droplet has
 settled), the droplet's aspect ratio from the second moments of its liquid excess, its area and
 the temperature range.
 """

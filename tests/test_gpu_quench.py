@@ -1,6 +1,6 @@
 """Quench with energy history (Sec. 3.2) on the GPU: the step at the run's own parameters
 (dt/tau = 1, dx = 1/256, the rings scaled for T near 1) against the FP64 oracle, and a short run
-of the driver whose per-step history is checked against the oracle's integrals."""
+of `quench.run` whose per-step history is checked against the oracle's integrals."""
 import numpy as np
 import pytest
 
