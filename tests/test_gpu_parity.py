@@ -319,6 +319,27 @@ def test_step_long_columns(torch_cuda, monkeypatch, prec, ypop, ymac):
         sim.close()
 
 
+@pytest.mark.parametrize("prec,ppb", [("fp64", "2"), ("fp32", "1"), ("fp32", "2"), ("fp32", "4")])
+def test_step_long_rows(torch_cuda, monkeypatch, prec, ppb):
+    # wide grids: x lines of 768 and 1536 points (radix-12 plans, the FP32 ones with all their
+    # twiddles preloaded) through the population x pass in each plan, three steps
+    monkeypatch.setenv("LBFFT_PPB", ppb)
+    tol = 1e-12 if prec == "fp64" else 2e-6
+    for nx, ny in ((768, 24), (1536, 12)):
+        p = W.base_params(q=-0.004, zeta=1e-3)
+        ic = W.smooth_random(nx, ny, 11 + nx, T0=0.52)
+        sim = _sim([(p, ic)], prec)
+        assert sim.plan(0)["pops_per_block_x"] == int(ppb)
+        f_ref = model.init_equilibrium(*ic, p)
+        for _ in range(3):
+            f_ref = model.rk2_step(f_ref, p)
+        sim.step(3)
+        errs = field_errors(sim.get_f(), f_ref, _moments(p))
+        say(f"long rows {nx}x{ny} {prec} pops/block {ppb} step 3: {errs}")
+        assert max(errs.values()) < tol, (nx, ny, errs)
+        sim.close()
+
+
 def test_multi_step_graph_matches_single_step_replays(torch_cuda, monkeypatch):
     # a single size class steps through a graph of several steps while enough remain; its state
     # must equal that of one-step replays bit for bit, history included (37 = 2 * 16 + 5)
