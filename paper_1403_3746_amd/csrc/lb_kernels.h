@@ -94,6 +94,11 @@ constexpr bool pop_y_wide_exists() {
 }
 template <typename T, int N>
 constexpr bool r16_exists() { return sizeof(T) == 4 && (N == 1024 || N == 2048); }
+// and of the population x pass: FP32 lines of 128 to 512 points held 4 elements per thread (twice
+// the threads per line: full 128-byte row segments per load instruction and half the registers
+// per line, for more passes through LDS)
+template <typename T, int N>
+constexpr bool popx_r4_exists() { return sizeof(T) == 4 && (N == 128 || N == 256 || N == 512); }
 
 __device__ __forceinline__ BlockWork decode_block(int ngroups, int ntiles, int njobs) {
     return decode_block_at(blockIdx.x, ngroups, ntiles, njobs);
@@ -577,13 +582,13 @@ constexpr int popx_waves(int N, int P) {
 // (c/tau) g, are one spectral multiplier (-c/tau + i (-c v_x k))/N, while the reference's own loss
 // -(c/tau) fref joins the gain: (c/tau)(f^eq - fref).  The equilibrium moments and the coefficient
 // loads of a cell are shared by the P populations.
-template <typename T, int N, int P>
-__global__ void __launch_bounds__((LineCfg<T, N, 0>::WG))
+template <typename T, int N, int P, int RR = 0>
+__global__ void __launch_bounds__((LineCfg<T, N, 0, 0, LB_YMAX_THREADS, RR>::WG))
 __attribute__((amdgpu_waves_per_eu(popx_waves<T>(N, P))))
 pop_x_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, int ngroups,
            int ntiles, const DvmConst<T>* __restrict__ dvm, const DvmConst<double>* __restrict__ dvm64,
            StageArgs st) {
-    using C = LineCfg<T, N, 0>;
+    using C = LineCfg<T, N, 0, 0, LB_YMAX_THREADS, RR>;
     constexpr int R = C::R, TPL = C::TPL;
     // the block's P lines are transformed together when their LDS fits the budget
     constexpr bool BATCH = P > 1 && P * C::LDS * (int)sizeof(cpx<T>) <= LB_POPX_BATCH_LDS;

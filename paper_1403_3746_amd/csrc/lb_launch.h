@@ -21,6 +21,7 @@ struct LaunchSet {
     // launch-plan variants (YVariant) of the population y pass and of the macroscopic y (or fused
     // x + y) passes, tuned per size class; used where they exist, else the default plan
     int ypop_var = 0, ymac_var = 0;
+    int xpop_var = 0;   // XVariant of the population x pass
 };
 
 // Launch through hipExtLaunchKernelGGL when the set carries timing events.
@@ -57,6 +58,10 @@ hipError_t pop_y_f32(const LaunchSet& L, const DvmConst<float>* dvm, const DvmCo
 // (lb_lines_y_<prec>.hip): YV_WIDE for the population pass, YV_R16 for both.
 int variants_y_f64(int n);
 int variants_y_f32(int n);
+// Bit mask of the XVariant plans of the population x pass that exist for x lines of n points
+// (lb_lines_x_<prec>.hip): XV_R4.
+int variants_x_f64(int n);
+int variants_x_f32(int n);
 
 // Fused x + y macroscopic passes of square grids (lb_lines_xy_<prec>.hip).
 hipError_t macro_xy_f64(const LaunchSet& L, const JobDesc* jx, int njx, const JobDesc* jy, int njy);

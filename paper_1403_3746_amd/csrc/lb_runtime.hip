@@ -177,6 +177,7 @@ struct lb_ctx {
         int nx, ny, start, count;
         int ppb = 1;   // tuned populations per block of the x population pass
         int ypop_var = 0, ymac_var = 0;   // tuned y-pass plan variants (YVariant) where they exist
+        int xpop_var = 0;                 // tuned x population pass plan (XVariant) where it exists
         bool hist = false;   // some instance keeps a per-step conservation history
     };
     std::vector<Class> classes;
@@ -190,6 +191,7 @@ struct lb_ctx {
     int ppb_override = 0;   // populations per x-pass block forced by LBFFT_PPB (1, 2 or 4), else tuned
     int ypop_override = -1;   // population y pass variant forced by LBFFT_YPOP (0, 1, 2), else tuned
     int ymac_override = -1;   // macroscopic y pass variant forced by LBFFT_YMAC (0, 2), else tuned
+    int xpop_override = -1;   // population x pass variant forced by LBFFT_XPOP (0, 1), else tuned
     bool fuse_xy = true;    // square grids: x and y macroscopic passes in one launch (LBFFT_FUSE_XY=0: off)
 
     template <typename Q>
@@ -258,6 +260,7 @@ void apply_plan(const lb_ctx& c, const lb_ctx::Class& k, LaunchSet& L) {
     L.ppb = c.ppb_override ? c.ppb_override : k.ppb;
     L.ypop_var = c.ypop_override >= 0 ? c.ypop_override : k.ypop_var;
     L.ymac_var = c.ymac_override >= 0 ? c.ymac_override : k.ymac_var;
+    L.xpop_var = c.xpop_override >= 0 ? c.xpop_override : k.xpop_var;
 }
 
 LaunchSet set_of(const lb_ctx& c, const lb_ctx::Class& k) {
@@ -277,6 +280,10 @@ LaunchSet set_one(const lb_ctx& c, int inst, hipStream_t s) {
 // Bit set (1 << YVariant) of the y-pass plan variants the class's y lines have.
 int class_variants(const lb_ctx& c, int ny) {
     return c.prec == LB_FP64 ? variants_y_f64(ny) : variants_y_f32(ny);
+}
+// Bit set (1 << XVariant) of the x population pass plans the class's x lines have.
+int class_variants_x(const lb_ctx& c, int nx) {
+    return c.prec == LB_FP64 ? variants_x_f64(nx) : variants_x_f32(nx);
 }
 
 // The x and y macroscopic passes of a square grid run as one fused launch, issued in the x slot.
@@ -500,28 +507,49 @@ hipError_t time_candidates(const lb_ctx& c, int ncand, Launch launch, float* bes
     return e;
 }
 
-// Launch plan of one size class, measured on the class's own data with stage-1 arguments (which
-// leave the state untouched): populations per block of the x population pass (1, 2, 4), then --
+// Launch plan of one size class, measured on the class's own data with arguments that leave the
+// state untouched: the x population pass in both stages' forms (populations per block 1, 2, 4 and,
+// where it exists, the 4-elements-per-thread plan, chosen together), then, with stage-1 arguments --
 // where the class's y lines have them -- the plan variants of the population y pass (default,
 // wide tiles, radix 16) and of the macroscopic y or fused x + y pass (default, radix 16).  Fixed
-// choices (LBFFT_PPB, LBFFT_YPOP, LBFFT_YMAC) are not re-tuned.
+// choices (LBFFT_PPB, LBFFT_YPOP, LBFFT_YMAC, LBFFT_XPOP) are not re-tuned.
 hipError_t tune_class(lb_ctx& c, lb_ctx::Class& cl) {
     const bool verbose = std::getenv("LBFFT_VERBOSE") != nullptr;
     LaunchSet L = set_of(c, cl);
     hipError_t e = force_passes(c, L, F_A);
     if (e != hipSuccess) return e;
     const StageArgs st{F_A, F_A, F_B, 0.5, 1};
-    float ms[3];
+    float ms[6];
     int best = 0;
-    if (!c.ppb_override) {
-        const int cand[3] = {1, 2, 4};
-        e = time_candidates(c, 3, [&](int k) { L.ppb = cand[k]; return pop_x(c, L, st); }, ms, &best);
+    // the x population pass: populations per block (1, 2, 4) and, where the class's x lines have
+    // it, the 4-elements-per-thread plan, chosen together
+    const bool x_r4 = (class_variants_x(c, cl.nx) & (1 << XV_R4)) != 0;
+    int pc[6], vc[6], nxc = 0;
+    for (int v : {XV_DEFAULT, XV_R4}) {
+        if ((v == XV_R4 && !x_r4) || (c.xpop_override >= 0 && v != c.xpop_override)) continue;
+        for (int p : {1, 2, 4}) {
+            if (c.ppb_override && p != c.ppb_override) continue;
+            pc[nxc] = p;
+            vc[nxc++] = v;
+        }
+    }
+    if (nxc > 1) {
+        // both stages' forms: the first folds the base into the transform, the second reads it per
+        // cell (here from F_B, written in place, so the state in F_A stays untouched)
+        const StageArgs st2{F_A, F_B, F_B, 1.0, 1};
+        e = time_candidates(c, nxc, [&](int k) {
+                L.ppb = pc[k];
+                L.xpop_var = vc[k];
+                hipError_t r = pop_x(c, L, st);
+                return r == hipSuccess ? pop_x(c, L, st2) : r;
+            }, ms, &best);
         if (e != hipSuccess) return e;
-        cl.ppb = cand[best];
+        cl.ppb = pc[best];
+        cl.xpop_var = vc[best];
         if (verbose)
-            for (int k = 0; k < 3; ++k)
-                std::fprintf(stderr, "lbfft tune: class %dx%d x%d  pops/block %d  %.4f ms\n", cl.nx,
-                             cl.ny, cl.count, cand[k], ms[k]);
+            for (int k = 0; k < nxc; ++k)
+                std::fprintf(stderr, "lbfft tune: class %dx%d x%d  pops/block %d  x variant %d  %.4f ms\n",
+                             cl.nx, cl.ny, cl.count, pc[k], vc[k], ms[k]);
     }
     L = set_of(c, cl);
     if ((e = pop_x(c, L, st)) != hipSuccess) return e;   // the partial sums the y pass adds to
@@ -731,6 +759,9 @@ lb_status lb_init(lb_ctx** out, int n_inst, const lb_params* p, const lb_dvm* dv
     if (const char* g = std::getenv("LBFFT_YMAC")) {
         if (g[0] == '0' || g[0] == '2') c->ymac_override = g[0] - '0';
     }
+    if (const char* g = std::getenv("LBFFT_XPOP")) {
+        if (g[0] == '0' || g[0] == '1') c->xpop_override = g[0] - '0';
+    }
 
     if (!build_dvm(c->dvm, c->dvm64)) {
         delete c;
@@ -891,7 +922,7 @@ lb_status lb_init(lb_ctx** out, int n_inst, const lb_params* p, const lb_dvm* dv
         if (!ok) break;
         const int64_t cells = (int64_t)cl.nx * cl.ny * cl.count;
         cl.ppb = cells >= (1 << 20) ? 2 : 1;   // default without tuning
-        if (tune && (!c->ppb_override || c->ypop_override < 0 || c->ymac_override < 0)) {
+        if (tune && (!c->ppb_override || c->ypop_override < 0 || c->ymac_override < 0 || c->xpop_override < 0)) {
             hipError_t e = tune_class(*c, cl);
             if (e != hipSuccess) {
                 ok = false;
@@ -1124,11 +1155,11 @@ lb_status lb_plan_info(lb_ctx* c, int inst, int* out, int n) {
     if (s != LB_OK) return s;
     if (!out || n < 2) return fail(LB_E_ARG, "need an output array of length >= 2");
     const LaunchSet L = set_one(*c, inst, c->stream);
-    // the variant a launch actually runs: the chosen one where it exists for the class's y lines
-    const int have = class_variants(*c, L.ny);
-    const int v[4] = {L.ppb, (int)c->classes.size(), (have >> L.ypop_var) & 1 ? L.ypop_var : 0,
-                      (have >> L.ymac_var) & 1 ? L.ymac_var : 0};
-    for (int k = 0; k < n && k < 4; ++k) out[k] = v[k];
+    // the variant a launch actually runs: the chosen one where it exists for the class's lines
+    const int have = class_variants(*c, L.ny), have_x = class_variants_x(*c, L.nx);
+    const int v[5] = {L.ppb, (int)c->classes.size(), (have >> L.ypop_var) & 1 ? L.ypop_var : 0,
+                      (have >> L.ymac_var) & 1 ? L.ymac_var : 0, (have_x >> L.xpop_var) & 1 ? L.xpop_var : 0};
+    for (int k = 0; k < n && k < 5; ++k) out[k] = v[k];
     return LB_OK;
 }
 

@@ -226,9 +226,10 @@ def lb_step_timed(ctx, n_steps):
 
 
 def lb_plan_info(ctx, inst):
-    out = (ctypes.c_int * 4)()
-    _check(load().lb_plan_info(ctx, inst, out, 4))
-    return dict(pops_per_block_x=out[0], size_classes=out[1], pop_y_plan=out[2], macro_y_plan=out[3])
+    out = (ctypes.c_int * 5)()
+    _check(load().lb_plan_info(ctx, inst, out, 5))
+    return dict(pops_per_block_x=out[0], size_classes=out[1], pop_y_plan=out[2], macro_y_plan=out[3],
+                pop_x_plan=out[4])
 
 
 def lb_free(ctx):

@@ -85,7 +85,8 @@ void run_case(const char* layout) {
             nr = std::max(nr, std::abs(std::complex<double>(xi[k].re, xi[k].im)));
         }
     }
-    std::printf("%s %d %s%s %d %.3e %.3e\n", sizeof(T) == 8 ? "f64" : "f32", N, layout, RR == 16 ? "16" : "", Q,
+    std::printf("%s %d %s%s %d %.3e %.3e\n", sizeof(T) == 8 ? "f64" : "f32", N, layout,
+                RR == 16 ? "16" : (RR == 4 ? "4" : ""), Q,
                 ef / nf, er / nr);
 }
 
@@ -134,6 +135,12 @@ void all_sizes() {
     run_case<T, 1024, 4, 4, 1, false, 16>("y");
     run_case<T, 2048, 2, 2, 1, false, 16>("y");
     run_case<T, 1024, 1, 2, 1, true, 16>("xw");
+    // 4 elements per thread for x lines of 128-512 points (the population x pass's alternative
+    // plan): two one-wave lines per wave, one line per wave, a line of two waves
+    run_case<T, 128, 1, 2, 1, true, 4>("xw");
+    run_case<T, 128, 1, 2, 2, false, 4>("x");
+    run_case<T, 256, 1, 1, 2, true, 4>("xw");
+    run_case<T, 512, 1, 1, 2, false, 4>("x");
 }
 
 int main() {

@@ -99,6 +99,7 @@ def test_batch128x256_fp32_step50(torch_cuda, monkeypatch):
     # The batch and the solo runs are created with the same forced launch plan, so each instance
     # of the batch must equal its solo run bit for bit; both are checked against the oracle.
     monkeypatch.setenv("LBFFT_PPB", "2")
+    monkeypatch.setenv("LBFFT_XPOP", "0")
     insts, _ = W.config("batch128x256")
     sim = _sim(insts, "fp32")
     say(f"batch plan: {sim.plan(0)}")

@@ -191,6 +191,7 @@ def test_ragged_batch_matches_solo_and_oracle(torch_cuda, monkeypatch):
     # oracle within the FP64 bar after 10 steps.  The launch plan is pinned: separately tuned
     # contexts may pick x-pass plans that round differently.
     monkeypatch.setenv("LBFFT_PPB", "2")
+    monkeypatch.setenv("LBFFT_XPOP", "0")
     insts = [(W.base_params(), W.slab(64, 64, 0.52)),
              (W.base_params(), W.quench(96, 96, 0.53, 5)),
              (W.base_params(q=-0.004), W.quench(64, 64, 0.55, 6)),
@@ -212,6 +213,7 @@ def test_ragged_batch_matches_solo_and_oracle(torch_cuda, monkeypatch):
 
 def test_step_timed_matches_graph_step(torch_cuda, monkeypatch):
     monkeypatch.setenv("LBFFT_PPB", "2")   # one plan for both contexts
+    monkeypatch.setenv("LBFFT_XPOP", "0")
     p = W.base_params()
     ic = W.quench(64, 48, 0.52, 9)
     a, b = _sim([(p, ic)]), _sim([(p, ic)], )
@@ -229,6 +231,7 @@ def test_fused_xy_passes_match_separate_passes(torch_cuda, monkeypatch):
     p = W.base_params()
     ic = W.quench(96, 96, 0.52, 21)
     monkeypatch.setenv("LBFFT_PPB", "2")   # same x-pass plan for both (no tuning difference)
+    monkeypatch.setenv("LBFFT_XPOP", "0")
     for prec in ("fp64", "fp32"):
         monkeypatch.setenv("LBFFT_FUSE_XY", "0")
         sep = _sim([(p, ic)], prec)
@@ -344,6 +347,7 @@ def test_multi_step_graph_matches_single_step_replays(torch_cuda, monkeypatch):
     # a single size class steps through a graph of several steps while enough remain; its state
     # must equal that of one-step replays bit for bit, history included (37 = 2 * 16 + 5)
     monkeypatch.setenv("LBFFT_PPB", "2")   # one plan for both contexts
+    monkeypatch.setenv("LBFFT_XPOP", "0")
     p = W.base_params(hist=64)
     ic = W.quench(64, 64, 0.9 * W.T_C, 11)
     out = {}
@@ -362,6 +366,7 @@ def test_ragged_multi_step_graph_matches_single_step_replays(torch_cuda, monkeyp
     # a batch of several size classes replays a graph of several steps whose class branches join
     # only at its end; states and histories must equal one-step replays bit for bit
     monkeypatch.setenv("LBFFT_PPB", "2")
+    monkeypatch.setenv("LBFFT_XPOP", "0")
     insts = [(W.base_params(hist=64), W.quench(64, 64, 0.9 * W.T_C, 12)),
              (W.base_params(), W.slab(96, 96, 0.52)),
              (W.base_params(hist=40), W.quench(128, 32, 0.53, 13)),
@@ -402,6 +407,28 @@ def test_fused_square_1024_fp32_every_y_plan(torch_cuda, monkeypatch, ymac):
     say(f"square 1024 fp32 macro y plan {ymac}: {errs}")
     assert errs["rho"] < 2e-6 and errs["T"] < 2e-6
     sim.close()
+
+
+@pytest.mark.parametrize("ppb", ["1", "2", "4"])
+def test_fp32_x_pass_four_elements_per_thread(torch_cuda, monkeypatch, ppb):
+    # the FP32 x population pass plan with 4 elements per thread (x lines of 128, 256 and 512
+    # points spread over twice the threads: one or two waves per line) in each populations-per-
+    # block setting, including a missing second row, two steps against the oracle
+    monkeypatch.setenv("LBFFT_PPB", ppb)
+    monkeypatch.setenv("LBFFT_XPOP", "1")
+    for ny, nx in ((24, 128), (16, 256), (8, 512), (1, 128), (2, 256)):
+        p = W.base_params(q=-0.004, zeta=1e-3)
+        ic = W.smooth_random(nx, ny, 500 + nx + ny, T0=0.52) if ny > 2 else W.slab(nx, ny, 0.52)
+        sim = _sim([(p, ic)], "fp32")
+        assert sim.plan(0)["pops_per_block_x"] == int(ppb) and sim.plan(0)["pop_x_plan"] == 1
+        f = model.init_equilibrium(*ic, p)
+        for _ in range(2):
+            f = model.rk2_step(f, p)
+        sim.step(2)
+        errs = field_errors(sim.get_f(), f, _moments(p))
+        say(f"fp32 x pass 4/thread, plan {ppb}, {nx}x{ny}: {errs}")
+        assert max(errs.values()) < 2e-6, (ppb, nx, ny, errs)
+        sim.close()
 
 
 @pytest.mark.parametrize("ppb", ["1", "2", "4"])
