@@ -202,14 +202,15 @@ lb_status lb_step_timed(lb_ctx* ctx, int n_steps, double ms[LB_NPASS]);
  *  out[0] = populations per block of the x population pass (1, 2 or 4),
  *  out[1] = size classes in the context,
  *  out[2] = plan of the population y pass: 0 default, 1 wide tiles (blocks of up to 1024
- *           threads, twice the column pairs of long columns), 2 radix 16 (16 elements per thread:
- *           half the threads per line, twice the column pairs per 512-thread block),
- *  out[3] = plan of the macroscopic y (or fused x + y) pass: 0 default, 2 radix 16,
+ *           threads, twice the column pairs of long columns), 2 long radix (16 elements per
+ *           thread for 1024 and 2048 points, 24 for 96, 192 and 384 points: fewer threads per
+ *           line, more column pairs per 512-thread block, fewer passes through LDS),
+ *  out[3] = plan of the macroscopic y (or fused x + y) pass: 0 default, 2 long radix,
  *  out[4] = plan of the population x pass: 0 default, 1 four elements per thread (twice the
  *           threads per line).
  * The variants exist in FP32, the wide tiles for y lines limited by the default 512-thread block,
- * radix 16 for lines of 1024 and 2048 points, four elements per thread for x lines of 128, 256 and
- * 512 points; elsewhere the entry is 0.
+ * the long radix for lines of 96, 192, 384, 1024 and 2048 points, four elements per thread for x
+ * lines of 128, 256 and 512 points; elsewhere the entry is 0.
  * n = length of out (>= 2; entries beyond min(n, 5) are not written). */
 lb_status lb_plan_info(lb_ctx* ctx, int inst, int* out, int n);
 

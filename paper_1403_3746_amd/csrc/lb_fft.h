@@ -1,4 +1,4 @@
-// Line FFT engine for gfx950: Stockham autosort mixed-radix (2, 3, 4, 8, 12, 16) transforms of complex
+// Line FFT engine for gfx950: Stockham autosort mixed-radix (2, 3, 4, 8, 12, 16, 24) transforms of complex
 // lines of length N held R elements per thread, exchanged through LDS between passes.
 //
 // A line is processed by N/R consecutive "line threads"; thread t holds elements t + m*(N/R),
@@ -147,6 +147,31 @@ struct Dft<T, 12, INV> {
     }
 };
 
+// 24-point DFT by the Good-Thomas split 24 = 3 x 8: input index n = (8 n1 + 3 n2) mod 24, output
+// index k = (16 k1 + 9 k2) mod 24, so W24^(nk) = W3^(n1 k1) W8^(n2 k2): eight 3-point DFTs over n1,
+// then three 8-point DFTs over n2, no twiddles between them.
+template <typename T, bool INV>
+struct Dft<T, 24, INV> {
+    __device__ __forceinline__ static void run(cpx<T>* v) {
+        cpx<T> y[8][3];
+#pragma unroll
+        for (int n2 = 0; n2 < 8; ++n2) {
+#pragma unroll
+            for (int n1 = 0; n1 < 3; ++n1) y[n2][n1] = v[(8 * n1 + 3 * n2) % 24];
+            Dft<T, 3, INV>::run(y[n2]);
+        }
+#pragma unroll
+        for (int k1 = 0; k1 < 3; ++k1) {
+            cpx<T> c[8];
+#pragma unroll
+            for (int n2 = 0; n2 < 8; ++n2) c[n2] = y[n2][k1];
+            Dft<T, 8, INV>::run(c);
+#pragma unroll
+            for (int k2 = 0; k2 < 8; ++k2) v[(16 * k1 + 9 * k2) % 24] = c[k2];
+        }
+    }
+};
+
 // a * W16^m, W16 = exp(-+ 2 pi i / 16) (forward / inverse), for the internal twiddles of the
 // 16-point DFT (m = n2 k1 <= 9); m is a constant after unrolling, so the switch folds away and the
 // eighth and quarter turns cost no general product.
@@ -215,6 +240,20 @@ constexpr Plan make_plan(int N, int R) {
     if (N == 2) {
         p.np = 1;
         p.r[0] = 2;
+        return p;
+    }
+    if (R == 24) {
+        // lines of 3 * 2^a points held 24 elements per thread: one radix-24 pass from the
+        // registers, then N/24 = 2^b in radix-8 passes, a radix-2 or radix-4 pass first where b is
+        // not a multiple of 3
+        p.r[p.np++] = 24;
+        int q = N / 24;
+        const int rem = 1 << (ilog2c(q) % 3);
+        if (rem > 1) {
+            p.r[p.np++] = rem;
+            q /= rem;
+        }
+        for (; q > 1; q /= 8) p.r[p.np++] = 8;
         return p;
     }
     if (R == 12) {

@@ -84,8 +84,10 @@ struct LineCfg {
 // 1024-thread block leaves 128 registers per thread, which the FP64 passes exceed):
 //   wide: the population y pass in blocks of up to LB_YMAX_THREADS_WIDE threads, where that holds
 //         more column pairs than the default (the macroscopic passes would spill);
-//   r16:  lines of 1024 and 2048 points held 16 elements per thread (radix-16 passes): half the
-//         threads per line, so a block of up to 512 threads holds twice the column pairs.
+//   long radix: lines of 1024 and 2048 points held 16 elements per thread (radix-16 passes), and
+//         lines of 3 * 2^a points from 96 to 384 held 24 (a radix-24 pass, then radix 8): fewer
+//         threads per line, so a block of up to 512 threads holds more column pairs, and fewer
+//         passes through LDS.
 template <typename T, int N>
 constexpr bool pop_y_wide_exists() {
     // lines of 3 * 2^a points hold 12 elements per thread and would spill at 1024 threads
@@ -93,7 +95,11 @@ constexpr bool pop_y_wide_exists() {
            LineCfg<T, N, 1, 0, LB_YMAX_THREADS_WIDE>::LPW != LineCfg<T, N, 1, 0, LB_YMAX_THREADS>::LPW;
 }
 template <typename T, int N>
-constexpr bool r16_exists() { return sizeof(T) == 4 && (N == 1024 || N == 2048); }
+constexpr bool r16_exists() {
+    return sizeof(T) == 4 && (N == 1024 || N == 2048 || (N % 3 == 0 && N >= 96 && N <= 384));
+}
+// elements per thread of that plan
+constexpr int long_R(int N) { return N % 3 == 0 ? 24 : 16; }
 // and of the population x pass: FP32 lines of 128 to 512 points held 4 elements per thread (twice
 // the threads per line: full 128-byte row segments per load instruction and half the registers
 // per line, for more passes through LDS)

@@ -86,7 +86,7 @@ void run_case(const char* layout) {
         }
     }
     std::printf("%s %d %s%s %d %.3e %.3e\n", sizeof(T) == 8 ? "f64" : "f32", N, layout,
-                RR == 16 ? "16" : (RR == 4 ? "4" : ""), Q,
+                RR == 16 ? "16" : (RR == 4 ? "4" : (RR == 24 ? "24" : "")), Q,
                 ef / nf, er / nr);
 }
 
@@ -141,6 +141,11 @@ void all_sizes() {
     run_case<T, 128, 1, 2, 2, false, 4>("x");
     run_case<T, 256, 1, 1, 2, true, 4>("xw");
     run_case<T, 512, 1, 1, 2, false, 4>("x");
+    // 24 elements per thread for lines of 3 * 2^a points (the long-radix y and fused plans)
+    run_case<T, 96, 16, 16, 1, false, 24>("y");
+    run_case<T, 384, 16, 16, 1, false, 24>("y");
+    run_case<T, 192, 1, 8, 1, true, 24>("xw");
+    run_case<T, 384, 1, 16, 1, true, 24>("xw");
 }
 
 int main() {

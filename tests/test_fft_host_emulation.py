@@ -1,7 +1,8 @@
 """The line FFT engine's own source (paper_1403_3746_amd/csrc/lb_fft.h) built for the CPU: every
 supported length, x and y block layouts, one line and several lines at a time, x blocks whose
 waves order their exchanges only among themselves, 16 elements per thread (radix-16 passes) for
-long lines, 4 elements per thread (the x pass's alternative plan for lines of 128-512 points),
+long lines, 24 elements per thread (a radix-24 pass) for lines of 3*2^a points, 4 elements per
+thread (the x pass's alternative plan for lines of 128-512 points),
 forward against a naive DFT (the discrete transform the windowed derivative of
 Eq. (3) is applied through) and forward-then-inverse against the input.  Runs without a GPU."""
 import os
@@ -35,8 +36,10 @@ def results(tmp_path_factory):
 def test_every_case_ran(results):
     sizes = {n for p, n, lay, q, _, _ in results if p == "f64" and lay == "x" and q == 1}
     assert sizes == {8, 12, 16, 24, 32, 48, 64, 96, 128, 192, 256, 384, 512, 768, 1024, 1536, 2048}
-    assert len(results) == 2 * 41
-    r4 = {(n, lay, q) for p, n, lay, q, _, _ in results if p == "f32" and lay.endswith("4") and not lay.endswith("16")}
+    assert len(results) == 2 * 45
+    r24 = {(n, lay) for p, n, lay, q, _, _ in results if p == "f32" and lay.endswith("24")}
+    assert r24 == {(96, "y24"), (384, "y24"), (192, "xw24"), (384, "xw24")}
+    r4 = {(n, lay, q) for p, n, lay, q, _, _ in results if p == "f32" and lay in ("x4", "xw4")}
     assert r4 == {(128, "xw4", 1), (128, "x4", 2), (256, "xw4", 2), (512, "x4", 2)}
     r16 = {(n, lay) for p, n, lay, q, _, _ in results if p == "f32" and lay.endswith("16")}
     assert r16 == {(512, "x16"), (1024, "x16"), (2048, "x16"), (1024, "y16"), (2048, "y16"), (1024, "xw16")}
