@@ -95,7 +95,7 @@ constexpr bool pop_y_wide_exists() {
            LineCfg<T, N, 1, 0, LB_YMAX_THREADS_WIDE>::LPW != LineCfg<T, N, 1, 0, LB_YMAX_THREADS>::LPW;
 }
 template <typename T, int N>
-constexpr bool r16_exists() {
+constexpr bool long_exists() {
     return sizeof(T) == 4 && (N == 1024 || N == 2048 || (N % 3 == 0 && N >= 96 && N <= 384));
 }
 // elements per thread of that plan

@@ -55,7 +55,7 @@ hipError_t pop_y_f32(const LaunchSet& L, const DvmConst<float>* dvm, const DvmCo
                      const int* pops, int npops, StageArgs st);
 
 // Bit set (1 << YVariant) of the launch-plan variants the y passes have for y lines of n points
-// (lb_lines_y_<prec>.hip): YV_WIDE for the population pass, YV_R16 for both.
+// (lb_lines_y_<prec>.hip): YV_WIDE for the population pass, YV_LONG for both.
 int variants_y_f64(int n);
 int variants_y_f32(int n);
 // Bit mask of the XVariant plans of the population x pass that exist for x lines of n points

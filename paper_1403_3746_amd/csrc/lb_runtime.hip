@@ -511,7 +511,7 @@ hipError_t time_candidates(const lb_ctx& c, int ncand, Launch launch, float* bes
 // state untouched: the x population pass in both stages' forms (populations per block 1, 2, 4 and,
 // where it exists, the 4-elements-per-thread plan, chosen together), then, with stage-1 arguments --
 // where the class's y lines have them -- the plan variants of the population y pass (default,
-// wide tiles, radix 16) and of the macroscopic y or fused x + y pass (default, radix 16).  Fixed
+// wide tiles, long radix) and of the macroscopic y or fused x + y pass (default, long radix).  Fixed
 // choices (LBFFT_PPB, LBFFT_YPOP, LBFFT_YMAC, LBFFT_XPOP) are not re-tuned.
 hipError_t tune_class(lb_ctx& c, lb_ctx::Class& cl) {
     const bool verbose = std::getenv("LBFFT_VERBOSE") != nullptr;
@@ -555,7 +555,7 @@ hipError_t tune_class(lb_ctx& c, lb_ctx::Class& cl) {
     if ((e = pop_x(c, L, st)) != hipSuccess) return e;   // the partial sums the y pass adds to
     const int have = class_variants(c, cl.ny);
     int cand[3] = {YV_DEFAULT, 0, 0}, nc = 1;
-    for (int v : {YV_WIDE, YV_R16})
+    for (int v : {YV_WIDE, YV_LONG})
         if (have & (1 << v)) cand[nc++] = v;
     if (c.ypop_override < 0 && nc > 1) {
         e = time_candidates(c, nc, [&](int k) { L.ypop_var = cand[k]; return pop_y(c, L, st); }, ms, &best);
@@ -567,8 +567,8 @@ hipError_t tune_class(lb_ctx& c, lb_ctx::Class& cl) {
                              cand[k], ms[k]);
     }
     L.ypop_var = cl.ypop_var;
-    if (c.ymac_override < 0 && (have & (1 << YV_R16))) {
-        const int mc[2] = {YV_DEFAULT, YV_R16};
+    if (c.ymac_override < 0 && (have & (1 << YV_LONG))) {
+        const int mc[2] = {YV_DEFAULT, YV_LONG};
         const int kind = fused_xy(c, L) ? LB_PASS_MACRO_X1 : LB_PASS_MACRO_Y1;
         e = time_candidates(c, 2, [&](int k) { L.ymac_var = mc[k]; return run_pass(c, L, kind, st); }, ms, &best);
         if (e != hipSuccess) return e;

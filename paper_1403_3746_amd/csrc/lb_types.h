@@ -72,9 +72,9 @@ inline constexpr bool line_ok(int n) {
 inline constexpr bool grid_ok(int nx, int ny) { return line_ok(nx) && (line_ok(ny) || ny == 1 || ny == 2); }
 
 // Launch-plan variants of the y passes (lb_kernels.h): the default plan, wide population y
-// tiles, radix-16 lines.
-// YV_R16: the long-radix plan, 16 elements per thread for 2^a lines and 24 for 3 * 2^a lines.
-enum YVariant : int { YV_DEFAULT = 0, YV_WIDE = 1, YV_R16 = 2 };
+// tiles, and the long-radix plan (YV_LONG: 16 elements per thread for 2^a lines, 24 for 3 * 2^a
+// lines).
+enum YVariant : int { YV_DEFAULT = 0, YV_WIDE = 1, YV_LONG = 2 };
 // Launch-plan variants of the population x pass: the default plan, 4 elements per thread.
 enum XVariant : int { XV_DEFAULT = 0, XV_R4 = 1 };
 

@@ -11,7 +11,7 @@ MXY(macro_xy_f64) MXY(macro_xy_f32)
 #define P(name, T) hipError_t name(const LaunchSet& L, const DvmConst<T>* d, const DvmConst<double>* d64, const int* p, int n, StageArgs) { chk(L); assert(d && d64 && p && n > 0); return hipSuccess; }
 P(pop_x_f64, double) P(pop_y_f64, double) P(pop_x_f32, float) P(pop_y_f32, float)
 int variants_y_f64(int) { return 0; }
-int variants_y_f32(int n) { return n >= 1024 ? (1 << YV_WIDE) | (1 << YV_R16) : 0; }
+int variants_y_f32(int n) { return n >= 1024 ? (1 << YV_WIDE) | (1 << YV_LONG) : 0; }
 int variants_x_f64(int) { return 0; }
 int variants_x_f32(int n) { return (n == 128 || n == 256 || n == 512) ? 1 << XV_R4 : 0; }
 template <typename T> hipError_t launch_moments(const LaunchSet& L, const DvmConst<double>*, int) { chk(L); return hipSuccess; }
