@@ -412,13 +412,13 @@ def test_fused_square_1024_fp32_every_y_plan(torch_cuda, monkeypatch, ymac):
 @pytest.mark.parametrize("ypop,ymac", [("2", "0"), ("0", "2"), ("2", "2")])
 def test_fp32_long_radix_plans_of_three_times_pow2(torch_cuda, monkeypatch, ypop, ymac):
     # the FP32 long-radix plans of 3*2^a lines (24 elements per thread: a radix-24 pass, then
-    # radix 8) in the population y pass and in the fused macroscopic pass, on square grids, two
-    # steps against the oracle
+    # radix 8) in the population y pass and in the macroscopic y pass -- fused with the x pass on
+    # square grids, separate on the others -- two steps against the oracle
     monkeypatch.setenv("LBFFT_YPOP", ypop)
     monkeypatch.setenv("LBFFT_YMAC", ymac)
-    for n in (96, 192, 384):
+    for nx, n in ((96, 96), (192, 192), (384, 384), (64, 192), (256, 96)):
         p = W.base_params(q=-0.004, zeta=1e-3)
-        ic = W.smooth_random(n, n, 700 + n, T0=0.52)
+        ic = W.smooth_random(nx, n, 700 + nx + n, T0=0.52)
         sim = _sim([(p, ic)], "fp32")
         assert sim.plan(0)["pop_y_plan"] == int(ypop) and sim.plan(0)["macro_y_plan"] == int(ymac)
         f = model.init_equilibrium(*ic, p)
@@ -426,8 +426,8 @@ def test_fp32_long_radix_plans_of_three_times_pow2(torch_cuda, monkeypatch, ypop
             f = model.rk2_step(f, p)
         sim.step(2)
         errs = field_errors(sim.get_f(), f, _moments(p))
-        say(f"fp32 long radix {n}x{n} y plans {ypop}/{ymac}: {errs}")
-        assert max(errs.values()) < 2e-6, (n, ypop, ymac, errs)
+        say(f"fp32 long radix {nx}x{n} y plans {ypop}/{ymac}: {errs}")
+        assert max(errs.values()) < 2e-6, (nx, n, ypop, ymac, errs)
         sim.close()
 
 
