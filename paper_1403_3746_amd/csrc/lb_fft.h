@@ -408,7 +408,10 @@ __device__ __forceinline__ void tw_fetch(twptr<T> table, int step, cpx<T>* d) {
 #ifndef LB_TW_PRELOAD_F32
 #define LB_TW_PRELOAD_F32 18  // float32: at most 18 (36 registers; the 384- and 768-point plans)
 #endif
-template <typename T, int N, int R>
+template <typename T>
+constexpr int tw_preload_limit() { return sizeof(T) == 4 ? LB_TW_PRELOAD_F32 : LB_TW_PRELOAD; }
+// PL: the preload limit, which a kernel may lower to spare registers
+template <typename T, int N, int R, int PL = tw_preload_limit<T>()>
 struct TwSet {
     static constexpr Plan P = make_plan(N, R);
     static constexpr int TPL = N / R;
@@ -419,7 +422,7 @@ struct TwSet {
         return o;
     }
     static constexpr int COUNT = offset(P.np);
-    static constexpr bool PRE = COUNT <= (sizeof(T) == 4 ? LB_TW_PRELOAD_F32 : LB_TW_PRELOAD);
+    static constexpr bool PRE = COUNT <= PL;
     cpx<T> w[PRE && COUNT > 0 ? COUNT : 1];
     twptr<T> table;
     int t;
@@ -457,10 +460,11 @@ struct TwSet {
 // Pass S of the plan: one Stockham pass of radix r = P.r[S] with Ns = product of the previous radices.
 // LDS element i of the line lives at lds[lds_idx(i) * LS]: LS = 1 for line-contiguous storage,
 // LS = lines per block for lines interleaved word by word (lanes of neighbouring lines adjacent).
-template <typename T, int N, int R, int S, bool INV, bool FROM_REG, bool TO_REG, int LS, bool WAVE = false>
-__device__ __forceinline__ void stockham_pass(cpx<T> (&v)[R], cpx<T>* lds, int t, const TwSet<T, N, R>& tw) {
-    constexpr int r = TwSet<T, N, R>::P.r[S];
-    constexpr int Ns = plan_ns(TwSet<T, N, R>::P, S);
+template <typename T, int N, int R, int S, bool INV, bool FROM_REG, bool TO_REG, int LS, bool WAVE = false, int PL = 0>
+__device__ __forceinline__ void stockham_pass(cpx<T> (&v)[R], cpx<T>* lds, int t, const TwSet<T, N, R, PL>& tw) {
+    using TW = TwSet<T, N, R, PL>;
+    constexpr int r = TW::P.r[S];
+    constexpr int Ns = plan_ns(TW::P, S);
     constexpr int TPL = N / R;
     constexpr int NB = R / r;
     static_assert(R % r == 0, "radix must divide R");
@@ -484,7 +488,7 @@ __device__ __forceinline__ void stockham_pass(cpx<T> (&v)[R], cpx<T>* lds, int t
         const int k = j % Ns;
         if constexpr (Ns > 1) {
             cpx<T> tb[tw_reads(r)], w[r];
-            if constexpr (TwSet<T, N, R>::PRE)
+            if constexpr (TW::PRE)
                 tw.template get<S>(b, tb);
             else
                 tw_fetch<T, r>(tw.table, k * (N / (Ns * r)), tb);
@@ -511,11 +515,12 @@ __device__ __forceinline__ void stockham_pass(cpx<T> (&v)[R], cpx<T>* lds, int t
 // powers formed once and applied to every line, and Q independent butterflies per twiddle set for
 // the scheduler to interleave.
 template <typename T, int N, int R, int S, bool INV, bool FROM_REG, bool TO_REG, int LS, int Q,
-          bool WAVE = false>
+          bool WAVE = false, int PL = 0>
 __device__ __forceinline__ void stockham_pass_n(cpx<T> (&v)[Q][R], cpx<T>* lds, int stride, int t,
-                                                const TwSet<T, N, R>& tw) {
-    constexpr int r = TwSet<T, N, R>::P.r[S];
-    constexpr int Ns = plan_ns(TwSet<T, N, R>::P, S);
+                                                const TwSet<T, N, R, PL>& tw) {
+    using TW = TwSet<T, N, R, PL>;
+    constexpr int r = TW::P.r[S];
+    constexpr int Ns = plan_ns(TW::P, S);
     constexpr int TPL = N / R;
     constexpr int NB = R / r;
     static_assert(R % r == 0, "radix must divide R");
@@ -543,7 +548,7 @@ __device__ __forceinline__ void stockham_pass_n(cpx<T> (&v)[Q][R], cpx<T>* lds, 
         const int k = j % Ns;
         if constexpr (Ns > 1) {
             cpx<T> tb[tw_reads(r)], w[r];
-            if constexpr (TwSet<T, N, R>::PRE)
+            if constexpr (TW::PRE)
                 tw.template get<S>(b, tb);
             else
                 tw_fetch<T, r>(tw.table, k * (N / (Ns * r)), tb);
@@ -573,11 +578,11 @@ __device__ __forceinline__ void stockham_pass_n(cpx<T> (&v)[Q][R], cpx<T>* lds, 
     if constexpr (!TO_REG) line_sync<WAVE>();
 }
 
-template <typename T, int N, int R, bool INV, int LS = 1, bool WAVE = false>
+template <typename T, int N, int R, bool INV, int LS = 1, bool WAVE = false, int PL = tw_preload_limit<T>()>
 struct LineFFT {
     static constexpr Plan P = make_plan(N, R);
     static constexpr int TPL = N / R;
-    using Tw = TwSet<T, N, R>;
+    using Tw = TwSet<T, N, R, PL>;
 
     template <int s>
     __device__ __forceinline__ static void passes(cpx<T> (&v)[R], cpx<T>* lds, int t, const Tw& tw) {

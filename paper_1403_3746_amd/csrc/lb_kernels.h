@@ -430,30 +430,35 @@ __device__ __forceinline__ void meq_unit(T ux, T uy, T Tm, T b, T (&m)[16]) {
     m[15] = h2 * Tm + h4 * uy * uy;
 }
 
+// f^eq_i from row c = (C^{-1})_i
 template <typename T>
-__device__ __forceinline__ T feq_dot(const DvmConst<T>& D, int i, T rho, const T (&m)[16]) {
+__device__ __forceinline__ T feq_row(const T (&c)[16], T rho, const T (&m)[16]) {
     T s = T(0);
 #pragma unroll
-    for (int j = 0; j < 16; ++j) s += D.cinv[i][j] * m[j];
+    for (int j = 0; j < 16; ++j) s += c[j] * m[j];
     return rho * s;
 }
+template <typename T>
+__device__ __forceinline__ T feq_dot(const DvmConst<T>& D, int i, T rho, const T (&m)[16]) {
+    return feq_row(D.cinv[i], rho, m);
+}
 
-// Equilibria of a mirror pair (i0, i1): i1 is i0 reflected in x (AX = 0) or y (AX = 1), so row i1
-// of C^{-1} is row i0 with the sign of the moments odd in v_x (resp. v_y) flipped.  With E, O the
-// even and odd parts of row i0's dot product, f^eq_i0 = rho (E + O) and f^eq_i1 = rho (E - O).
-// Odd moments in the row order of meq_unit: v_x -> 1, 5, 7, 9, 11, 14; v_y -> 2, 5, 8, 10, 12, 14.
+// Equilibria of a mirror pair (i0, i1) from row c = (C^{-1})_i0: i1 is i0 reflected in x (AX = 0)
+// or y (AX = 1), so row i1 of C^{-1} is row i0 with the sign of the moments odd in v_x (resp. v_y)
+// flipped.  With E, O the even and odd parts of row i0's dot product, f^eq_i0 = rho (E + O) and
+// f^eq_i1 = rho (E - O).  Odd moments in the row order of meq_unit: v_x -> 1, 5, 7, 9, 11, 14;
+// v_y -> 2, 5, 8, 10, 12, 14.
 template <typename T, int AX>
-__device__ __forceinline__ void feq_mirror_pair(const DvmConst<T>& D, int i0, T rho,
-                                                const T (&m)[16], T& fe0, T& fe1) {
+__device__ __forceinline__ void feq_mirror_row(const T (&c)[16], T rho, const T (&m)[16], T& fe0, T& fe1) {
     constexpr unsigned ODD = AX == 0 ? ((1u << 1) | (1u << 5) | (1u << 7) | (1u << 9) | (1u << 11) | (1u << 14))
                                      : ((1u << 2) | (1u << 5) | (1u << 8) | (1u << 10) | (1u << 12) | (1u << 14));
     T e = T(0), o = T(0);
 #pragma unroll
     for (int j = 0; j < 16; ++j) {
         if ((ODD >> j) & 1u)
-            o += D.cinv[i0][j] * m[j];
+            o += c[j] * m[j];
         else
-            e += D.cinv[i0][j] * m[j];
+            e += c[j] * m[j];
     }
     fe0 = rho * (e + o);
     fe1 = rho * (e - o);
@@ -525,6 +530,23 @@ struct PopXEpi {
     // pairs rot(i) at the turned velocity (u_y, -u_x).  v[0] holds the first group's inputs
     // (requested by the caller with load(0, v[0]), possibly before the transforms).
     __device__ __forceinline__ void run(const cpx<T> (&X)[P][R], bool rotu, T (&v)[2][G][NV]) const {
+        // The block's constants, read once into registers: read through D inside the cell loop,
+        // they would be fetched again after every store (a buffer store may alias any memory).
+        constexpr int NR = P == 1 ? 1 : P / 2;
+        E crow[NR][16];   // C^{-1} row of the population, or of each pair's first population
+        T pvx[P], pvy[P], pwe[P];
+#pragma unroll
+        for (int r = 0; r < NR; ++r) {
+            const int i = P == 1 ? pop[0] : (rotu ? D.rot[pop[2 * r]] : pop[2 * r]);
+#pragma unroll
+            for (int j = 0; j < 16; ++j) crow[r][j] = DE.cinv[i][j];
+        }
+#pragma unroll
+        for (int q = 0; q < P; ++q) {
+            pvx[q] = D.vx[pop[q]];
+            pvy[q] = D.vy[pop[q]];
+            pwe[q] = D.w[pop[q]] - D.eta2[pop[q]];
+        }
 #pragma unroll
         for (int g = 0; g < NG; ++g) {
             if (g + 1 < NG) load(g + 1, v[(g + 1) & 1]);
@@ -545,22 +567,20 @@ struct PopXEpi {
                 E fe[P];
                 if constexpr (P == 1) {
                     meq_unit<E>(E(ux), E(uy), TmE, b, mq);
-                    fe[0] = feq_dot(DE, pop[0], E(rho), mq);
+                    fe[0] = feq_row(crow[0], E(rho), mq);
                 } else {
                     meq_unit<E>(E(rotu ? uy : ux), E(rotu ? -ux : uy), TmE, b, mq);
 #pragma unroll
-                    for (int q = 0; q < P; q += 2)
-                        feq_mirror_pair<E, 0>(DE, rotu ? D.rot[pop[q]] : pop[q], E(rho), mq, fe[q], fe[q + 1]);
+                    for (int q = 0; q < P; q += 2) feq_mirror_row<E, 0>(crow[q / 2], E(rho), mq, fe[q], fe[q + 1]);
                 }
                 const uint32_t e = cell(k);
 #pragma unroll
                 for (int q = 0; q < P; ++q) {
-                    const int i = pop[q];
                     // relaxation towards f^eq of the deviation from the reference: the loss of
                     // the reference itself, -ct fref, joins the gain ct f^eq
                     const T feq = T(fe[q]);
                     const T dfeq = T(fe[q] - fref[q]);
-                    const T gq = h0 + hx * D.vx[i] + hy * D.vy[i] + hv * (D.w[i] - D.eta2[i]);
+                    const T gq = h0 + hx * pvx[q] + hy * pvy[q] + hv * pwe[q];
                     const T lin = h == 0 ? X[q][m].re : X[q][m].im;
                     const T base = has_base ? x[7 + q] : T(0);
                     const T out = base + lin + ct * dfeq + c * (feq * gq);
@@ -737,18 +757,25 @@ pop_y_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
 
     // the line, the twiddles and the wavenumbers (and in FP32 the partial sums the result is
     // added to) are requested before the transforms so that their latencies overlap; in FP64 the
-    // partial sums are read after the transforms, all before the first store, to spare registers
-    constexpr bool EARLY = sizeof(T) == 4;
+    // partial sums are read after the transforms, all before the first store, to spare registers.
+    // The FP32 long-radix plans (16 or 24 elements per thread) spare registers the same way and
+    // read each pass's twiddles when the pass runs: at 1024 and 2048 points that leaves them 121
+    // registers instead of 164-177, four waves per SIMD instead of two or three.
+    constexpr bool LONG = sizeof(T) == 4 && R >= 16;
+    constexpr bool EARLY = sizeof(T) == 4 && !LONG;
+    constexpr int PL = LONG ? 0 : tw_preload_limit<T>();
+    using FFT = LineFFT<T, N, R, false, C::LS, false, PL>;
+    using IFFT = LineFFT<T, N, R, true, C::LS, false, PL>;
     cpx<T> X[R];
     load_line<T, 1, R, TPL>(fieldp<T>(I, st.f_field + i), X, line, t, nx, ny, active);
     cpx<T> Pv[R];
     if constexpr (EARLY) load_line<T, 1, R, TPL>(fieldp<T>(I, F_P + i), Pv, line, t, nx, ny, active);
-    typename LineFFT<T, N, R, false, C::LS>::Tw tws;
+    typename FFT::Tw tws;
     tws.load(tw, t);
     const LB_GLOBAL T* kap = gcast(reinterpret_cast<const T*>(I.ky));
     Wavenum<T, R, TPL> kv;
     kv.load(kap, t);
-    LineFFT<T, N, R, false, C::LS>::run(X, lds, t, tws);
+    FFT::run(X, lds, t, tws);
     const T s = -T(st.use_dt ? st.alpha * I.dt : st.alpha) * vy * T(1.0 / N);
 #pragma unroll
     for (int m = 0; m < R; ++m) {
@@ -756,7 +783,7 @@ pop_y_pass(const InstDesc* __restrict__ insts, const int* __restrict__ ilist, in
         const cpx<T> x = X[m];
         X[m] = {-a * x.im, a * x.re};
     }
-    LineFFT<T, N, R, true, C::LS>::run(X, lds, t, tws);
+    IFFT::run(X, lds, t, tws);
     if (!active) return;
     if constexpr (!EARLY) load_line<T, 1, R, TPL>(fieldp<T>(I, F_P + i), Pv, line, t, nx, ny, true);
     LB_GLOBAL T* out = fieldp<T>(I, st.out_field + i);
