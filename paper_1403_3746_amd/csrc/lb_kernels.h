@@ -487,7 +487,7 @@ __device__ __forceinline__ T feq_pop(const DvmConst<T>& D, int i, T rho, T ux, T
 #define LB_EPI_CELLS_F64 2
 #endif
 #ifndef LB_EPI_CELLS_F32
-#define LB_EPI_CELLS_F32 4
+#define LB_EPI_CELLS_F32 2
 #endif
 template <typename T, int R, int TPL, int P>
 struct PopXEpi {
