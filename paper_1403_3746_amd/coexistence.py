@@ -141,12 +141,14 @@ def main(argv=None):
     ap.add_argument("--K", type=float, default=PAPER_PARAMS["K"],
                     help="surface-tension coefficient (the Sec. 3.1 value by default)")
     ap.add_argument("--nx", type=int, default=512)
+    ap.add_argument("--dx", type=float, default=PAPER_PARAMS["dx"],
+                    help="grid spacing (with --nx: the same slab at another resolution)")
     ap.add_argument("--ring-scale", type=float, default=1.15,
                     help="ring speeds (1, 0.5, 2, 1) times this factor (the paper does not print them)")
     ap.add_argument("--json", help="write the records here")
     a = ap.parse_args(argv)
     recs = run(a.temperatures, a.precision, nx=a.nx, check=a.check, window=a.window, tol=a.tol,
-               max_steps=a.max_steps, hold=not a.no_hold, params=dict(K=a.K),
+               max_steps=a.max_steps, hold=not a.no_hold, params=dict(K=a.K, dx=a.dx),
                dvm=scaled_rings(a.ring_scale), log=lambda s: print(s, flush=True))
     for r in recs:
         print(json.dumps(r), flush=True)
