@@ -109,8 +109,12 @@ def main(argv=None):
     ap.add_argument("--every", type=int, default=1000, help="keep e_T every this many steps")
     ap.add_argument("--json", help="write the summary (history, snapshot statistics) here")
     ap.add_argument("--npz", help="write the density snapshots here")
+    ap.add_argument("--n", type=int, default=128, help="cells per side")
+    ap.add_argument("--dx", type=float, default=PAPER_PARAMS["dx"],
+                    help="grid spacing (with --n: the same domain at another resolution)")
     a = ap.parse_args(argv)
-    r = run(a.t_end, a.precision, every=a.every, log=lambda s: print(s, flush=True))
+    r = run(a.t_end, a.precision, n=a.n, every=a.every, params=dict(dx=a.dx),
+            log=lambda s: print(s, flush=True))
     summary = {k: v for k, v in r.items() if k != "rho"}
     print(json.dumps({k: v for k, v in summary.items() if k not in ("times", "e_T")}), flush=True)
     if a.json:
